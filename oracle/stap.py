@@ -1,0 +1,196 @@
+"""CPU FP64 oracle of the post-Doppler STAP hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the bench's
+CPU-baseline leg may import this module; the GPU library never does.  It shares
+no code, table or constant with the HIP kernels.
+
+It is written to be checked by eye: complex128 NumPy/SciPy, one processing
+step per function, in the order the steps are defined, with no blocking,
+fusion or reordering.  Library primitives (``numpy.fft.fft``, ``@``,
+``numpy.linalg.solve``, ``numpy.linalg.cholesky``) serve as single steps.
+
+Source.  Shirako et al., "Automatic Parallelization of Python Programs for
+Distributed Heterogeneous Computing" (arXiv 2203.06233), Sec. 4.2 and the
+figure "Kernel from the STAP Signal Processing Application": the STAP kernel is
+an explicit loop (statement S), an ``fft`` along one axis (statement T; Table 2
+row fft_{2D,axis=1}: every row of the operand is transformed) and a
+2-D x 2-D array multiply (statement U; Table 2 row dot_{2D,2D}), all fused into
+one parallel loop over independent units.  Sec. 5.3 states the problem as
+datacubes of pulses x channels x samples per pulse and cites Melvin (2014) for
+STAP.  The figure's code is not reproduced in the paper's text, so the steps
+below follow textbook post-Doppler STAP with time-staggered DOF.  Readings the
+paper leaves open, each chosen once and used on both sides:
+
+* Doppler: T taps; tap t applies a symmetric Hann window of length
+  L = P - T + 1 placed at pulses t .. t+L-1, then a length-P DFT with kernel
+  exp(-j 2 pi k p / P), unnormalised, bins in natural order; DOF index
+  d = t*C + c.
+* Training: B contiguous blocks of N = R/B range cells; block b's covariance
+  is the mean outer product of its own snapshots (cell under test included).
+* Loading: delta = eps * Re tr(R_hat) / D added to the diagonal.
+* Weights: adaptive matched filter, w = R_L^-1 v / sqrt(v^H R_L^-1 v).
+* Output: y = w^H x per cell, power |y|^2.
+
+Every function below is pinned by tests against brute force, closed forms,
+invariants and library routines (see tests/test_oracle_pins.py).
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional
+
+import numpy as np
+
+
+def hann(L: int) -> np.ndarray:
+    """Symmetric Hann window h[n] = 1/2 - 1/2 cos(2 pi n / (L-1)), n = 0..L-1."""
+    n = np.arange(L, dtype=np.float64)
+    return 0.5 - 0.5 * np.cos(2.0 * np.pi * n / (L - 1))
+
+
+def tap_windows(P: int, T: int) -> np.ndarray:
+    """Windows of the T time-staggered taps, ``[T][P]``: h_t[p] = h[p - t]."""
+    L = P - T + 1
+    h = hann(L)
+    W = np.zeros((T, P), np.float64)
+    for t in range(T):
+        W[t, t:t + L] = h
+    return W
+
+
+def doppler(cube: np.ndarray, T: int) -> np.ndarray:
+    """Doppler filtering (statements S and T): snapshots ``X[k][t*C + c][r]``.
+
+    X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k p / P).
+    """
+    C, P, R = cube.shape
+    x = cube.astype(np.complex128)
+    W = tap_windows(P, T)
+    X = np.empty((P, T * C, R), np.complex128)
+    for t in range(T):
+        Xt = np.fft.fft(x * W[t][None, :, None], axis=1)  # [C][k][R]
+        X[:, t * C:(t + 1) * C, :] = Xt.transpose(1, 0, 2)
+    return X
+
+
+def covariance(X: np.ndarray, n_block: int) -> np.ndarray:
+    """Sample covariance per (Doppler bin, training block) (statement U).
+
+    R_hat[k][b] = (1/N) sum_{r in block b} X[k][:, r] X[k][:, r]^H.
+    """
+    P, D, R = X.shape
+    N = R // n_block
+    Xb = X.reshape(P, D, n_block, N).transpose(0, 2, 1, 3)  # [k][b][d][n]
+    return (Xb @ np.conj(Xb).swapaxes(-1, -2)) / N
+
+
+def loading(R_hat: np.ndarray, eps: float):
+    """Diagonal loading: delta = eps * Re tr(R_hat) / D; R_L = R_hat + delta I."""
+    D = R_hat.shape[-1]
+    tr = np.real(np.trace(R_hat, axis1=-2, axis2=-1))
+    delta = eps * tr / D
+    R_L = R_hat + delta[..., None, None] * np.eye(D)
+    return delta, R_L
+
+
+def cholesky_info(A: np.ndarray):
+    """Lower Cholesky factor of one Hermitian matrix, LAPACK-style status.
+
+    Returns (L, info): info = 0 on success, else j >= 1, the 1-based index of
+    the first pivot that is not positive (L is then undefined).  Textbook
+    column-by-column (left-looking) factorisation: L[j][j] = sqrt(A[j][j] -
+    sum_k |L[j][k]|^2); L[i][j] = (A[i][j] - sum_k L[i][k] conj(L[j][k])) /
+    L[j][j].  Only used where a status is needed; the batched path below uses
+    numpy.linalg.cholesky for speed and falls back here on failure.
+    """
+    D = A.shape[0]
+    L = np.zeros_like(A, dtype=np.complex128)
+    for j in range(D):
+        piv = np.real(A[j, j]) - np.sum(np.abs(L[j, :j]) ** 2)
+        if not (piv > 0.0) or not np.isfinite(piv):
+            return L, j + 1
+        L[j, j] = np.sqrt(piv)
+        L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ np.conj(L[j, :j])) / L[j, j]
+    return L, 0
+
+
+def solve_weights(R_L: np.ndarray, V: np.ndarray):
+    """Adaptive matched-filter weights for every system and steering vector.
+
+    R_L ``[..][D][D]`` loaded covariances, V ``[S][D]`` steering set.
+    u_s = R_L^-1 v_s; gamma_s = Re(v_s^H u_s); w_s = u_s / sqrt(gamma_s).
+    The weights are defined by the solve, so a general dense solve
+    (``numpy.linalg.solve``) computes them; the Cholesky factorisation is used
+    only for the status: info = 0 where R_L = L L^H exists, else the 1-based
+    index of the first pivot that is not positive, and those systems get zero
+    weights.  Returns (W ``[..][S][D]``, gamma ``[..][S]``, info ``[..]``).
+    """
+    batch = R_L.shape[:-2]
+    D = R_L.shape[-1]
+    S = V.shape[0]
+    flat = R_L.reshape(-1, D, D)
+    info = np.zeros(flat.shape[0], np.int32)
+    try:
+        np.linalg.cholesky(flat)
+    except np.linalg.LinAlgError:
+        for i in range(flat.shape[0]):
+            info[i] = cholesky_info(flat[i])[1]
+    ok = info == 0
+    W = np.zeros((flat.shape[0], S, D), np.complex128)
+    G = np.zeros((flat.shape[0], S), np.float64)
+    if np.any(ok):
+        Vt = V.astype(np.complex128).T                       # [D][S]
+        u = np.linalg.solve(flat[ok], Vt[None])              # [..][D][S]
+        gamma = np.real(np.sum(np.conj(Vt)[None] * u, axis=1))  # [..][S]
+        W[ok] = (u / np.sqrt(gamma)[:, None, :]).swapaxes(1, 2)
+        G[ok] = gamma
+    return W.reshape(*batch, S, D), G.reshape(*batch, S), info.reshape(batch)
+
+
+def inner_products(W: np.ndarray, X: np.ndarray, n_block: int):
+    """Output y[k][s][r] = w_{k, b(r), s}^H X[k][:, r]; power |y|^2.
+
+    W ``[P][B][S][D]``, X ``[P][D][R]``.  Returns (y, power) ``[P][S][R]``.
+    """
+    P, D, R = X.shape
+    N = R // n_block
+    Xb = X.reshape(P, D, n_block, N).transpose(0, 2, 1, 3)  # [k][b][d][n]
+    Yb = np.conj(W) @ Xb                                     # [k][b][s][n]
+    y = Yb.transpose(0, 2, 1, 3).reshape(P, W.shape[2], R)
+    return y, np.abs(y) ** 2
+
+
+def run(cube: np.ndarray, V: np.ndarray, T: int, n_block: int, eps: float,
+        keep: bool = True) -> Dict[str, np.ndarray]:
+    """The whole chain on one cube ``[C][P][R]`` with steering set ``[S][D]``."""
+    X = doppler(cube, T)
+    R_hat = covariance(X, n_block)
+    delta, R_L = loading(R_hat, eps)
+    W, gamma, info = solve_weights(R_L, V)
+    y, power = inner_products(W, X, n_block)
+    out = dict(W=W, gamma=gamma, info=info, delta=delta, y=y, power=power)
+    if keep:
+        out.update(X=X, R_hat=R_hat, R_L=R_L)
+    return out
+
+
+def run_block(cube_block: np.ndarray, V: np.ndarray, T: int, eps: float,
+              bins: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """The chain for ONE training block: ``cube_block`` is ``[C][P][N]``.
+
+    Doppler filtering acts on each (channel, range cell) column alone, so the
+    block's snapshots need only its own cells; ``bins`` selects Doppler bins.
+    Returns arrays indexed [k][...] over the selected bins with B = 1.
+    """
+    X = doppler(cube_block, T)
+    if bins is not None:
+        X = X[np.asarray(bins)]
+    return run_from_snapshots(X, V, 1, eps)
+
+
+def run_from_snapshots(X: np.ndarray, V: np.ndarray, n_block: int, eps: float):
+    R_hat = covariance(X, n_block)
+    delta, R_L = loading(R_hat, eps)
+    W, gamma, info = solve_weights(R_L, V)
+    y, power = inner_products(W, X, n_block)
+    return dict(X=X, R_hat=R_hat, R_L=R_L, delta=delta, W=W, gamma=gamma,
+                info=info, y=y, power=power)
