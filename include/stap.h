@@ -1,0 +1,175 @@
+/*
+ * stap.h -- C ABI of the MI355X (gfx950) STAP hot-path library (libstap.so).
+ *
+ * The library computes post-Doppler space-time adaptive processing (STAP) for
+ * radar datacubes, the application whose kernel the paper parallelises:
+ * Shirako et al., "Automatic Parallelization of Python Programs for
+ * Distributed Heterogeneous Computing", arXiv 2203.06233.  Sec. 5.3 states the
+ * problem: datacubes of pulses x channels x samples (range cells) per pulse.
+ * Sec. 4.2 and the figure "Kernel from the STAP Signal Processing Application"
+ * describe the kernel as an explicit loop (statement S), an fft along one axis
+ * (statement T; Table 2, row fft_{2D,axis=1}) and a 2-D x 2-D array multiply
+ * (statement U; Table 2, row dot_{2D,2D}), fused into one parallel loop over
+ * independent units.  The step definitions below are textbook post-Doppler
+ * STAP (Melvin 2014, the paper's STAP reference) under these readings:
+ *
+ *   Doppler    X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k p / P),
+ *              h_t[p] = h[p-t] for t <= p < t+L, L = P-T+1, h the symmetric
+ *              Hann window h[n] = 1/2 - 1/2 cos(2 pi n/(L-1)); k = 0..P-1.
+ *   Covariance R_hat[k][b] = (1/N) sum_{r in block b} X[k][:,r] X[k][:,r]^H,
+ *              blocks of N = R/B contiguous range cells.
+ *   Loading    delta = eps * Re tr(R_hat) / D,  R_L = R_hat + delta I.
+ *   Weights    R_L = L L^H (Cholesky),  u_s = R_L^-1 v_s,
+ *              gamma_s = Re(v_s^H u_s),  w_s = u_s / sqrt(gamma_s).
+ *   Output     y[k][s][r] = w_{k,b(r),s}^H X[k][:,r],  power = |y|^2.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers owned by the caller; the library
+ *     never allocates, frees or copies to the host on these calls.  Work is
+ *     enqueued on `stream` (a hipStream_t, 0 = the null stream) and the call
+ *     returns without synchronising.
+ *   - Complex values are stap_cf32 {re, im} (bit-compatible with
+ *     std::complex<float>, numpy complex64 and torch.complex64).
+ *   - Arrays are dense, row-major, last index fastest, in the layouts given
+ *     with each argument.  Device pointers must be 16-byte aligned
+ *     (STAP_ERR_ALIGN otherwise).
+ *   - Argument, shape, alignment and workspace errors are detected on the
+ *     host before anything is enqueued and return a negative stap_status.
+ *     A numerical failure (a pivot of the Cholesky factorisation that is not
+ *     positive) is reported per system in `info` (LAPACK potrf convention:
+ *     0 = success, j > 0 = 1-based index of the first bad pivot); that
+ *     system's weights and output power are zero and the call still returns
+ *     STAP_OK.
+ *   - Limits: n_pulse P a power of two in [32, 512]; 1 <= tdof T <= 4 and
+ *     T < P; D = T*C <= 192; n_range R divisible by n_block B; 1 <= S <= 64.
+ */
+#ifndef STAP_H
+#define STAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stap_cf32 {
+  float re, im;
+} stap_cf32;
+
+typedef enum stap_status {
+  STAP_OK = 0,
+  STAP_ERR_ARG = -1,          /* null pointer or value out of range */
+  STAP_ERR_SHAPE = -2,        /* dimensions outside the supported limits */
+  STAP_ERR_ALIGN = -3,        /* a device pointer is not 16-byte aligned */
+  STAP_ERR_WORKSPACE = -4,    /* workspace missing or smaller than needed */
+  STAP_ERR_HIP = -5,          /* a HIP runtime call failed (launch, query) */
+  STAP_ERR_UNSUPPORTED = -6   /* valid request this build does not handle */
+} stap_status;
+
+typedef enum stap_precision {
+  /* FP32 throughout: FP32 FFT, FP32 covariance on FP32 MFMA, FP32
+   * Cholesky/solves, FP32 inner products. */
+  STAP_PREC_FP32 = 0,
+  /* Mixed: covariance and inner products as BF16 MFMA products with FP32
+   * accumulation (each FP32 operand split exactly into three BF16 terms),
+   * FP32 Cholesky/solves, FP64 refinement residual. */
+  STAP_PREC_BF16 = 1,
+  /* As BF16 but the covariance is one FP8 (OCP E4M3) product per element
+   * with a power-of-two scale per (bin, block) and FP32 accumulation. */
+  STAP_PREC_FP8 = 2
+} stap_precision;
+
+/* One datacube's problem statement (Sec. 5.3: pulses x channels x samples),
+ * plus the adaptive-processing parameters. */
+typedef struct stap_problem {
+  int32_t n_chan;        /* C: receive channels */
+  int32_t n_pulse;       /* P: pulses per CPI = FFT length = Doppler bins */
+  int32_t n_range;       /* R: range cells (samples per pulse) */
+  int32_t tdof;          /* T: time-staggered taps (temporal DOF); D = T*C */
+  int32_t n_block;       /* B: training blocks along range, N = R/B cells */
+  int32_t n_steer;       /* S: steering vectors */
+  float load_eps;        /* eps >= 0: loading delta = eps * tr(R_hat) / D */
+  int32_t precision;     /* stap_precision */
+  int32_t refine_steps;  /* FP64 iterative-refinement steps, 0..4 */
+  int32_t reserved;      /* must be 0 */
+  int64_t cube_stride_chan;   /* elements between channels of `cube`; 0 = P*R */
+  int64_t cube_stride_pulse;  /* elements between pulses of `cube`; 0 = R.
+                                 The range stride is always 1. */
+} stap_problem;
+
+/* Doppler filtering with time-staggered DOF (statements S and T of the
+ * paper's kernel, Sec. 4.2; Table 2 row fft_{2D,axis=1}).
+ *   cube  in : x[C][P][R] complex, strides from `prob` (range stride 1).
+ *   snap  out: X[P][D][R] complex, D = T*C, d = t*C + c, bins k = 0..P-1.
+ * FP32 arithmetic for every precision. */
+stap_status stap_doppler(const stap_problem* prob, const stap_cf32* cube,
+                         stap_cf32* snap, void* stream);
+
+/* Sample covariance per (Doppler bin, training block) with diagonal loading
+ * (statement U, Sec. 4.2; Table 2 row dot_{2D,2D}).
+ *   snap  in : X[P][D][R] as written by stap_doppler.
+ *   cov   out: R_L[P][B][D][D], full Hermitian (both triangles; the upper is
+ *              the conjugate of the lower, bit for bit), loading included.
+ *   delta out: delta[P][B] float, may be NULL.
+ * Arithmetic per prob->precision (FP32 MFMA, split-BF16 MFMA or scaled FP8
+ * MFMA, FP32 accumulation); the trace for the loading is summed in FP64. */
+stap_status stap_covariance(const stap_problem* prob, const stap_cf32* snap,
+                            stap_cf32* cov, float* delta, void* stream);
+
+/* Adaptive weights by Cholesky solves (the textbook STAP weight solve).
+ *   cov   in : R_L[P][B][D][D] Hermitian; only the lower triangle is read.
+ *   steer in : V[S][D] steering vectors.
+ *   w     out: W[P][B][S][D], w_s = R_L^-1 v_s / sqrt(v_s^H R_L^-1 v_s).
+ *   info  out: info[P][B] int32 (0 = ok, j = first non-positive pivot).
+ * FP32 factorisation and triangular solves; prob->refine_steps steps of
+ * iterative refinement whose residual v - R_L u is formed in FP64. */
+stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov,
+                               const stap_cf32* steer, stap_cf32* w,
+                               int32_t* info, void* stream);
+
+/* Weight x snapshot inner products and output power (statement U applied to
+ * the weights; the adaptive filter output).
+ *   w     in : W[P][B][S][D];  snap in: X[P][D][R].
+ *   power out: |y|^2 as float [P][S][R].
+ *   y     out: y[P][S][R] complex, may be NULL. */
+stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
+                                const stap_cf32* snap, float* power,
+                                stap_cf32* y, void* stream);
+
+/* The whole chain (Doppler -> covariance -> weights -> output) for n_probs
+ * independent cubes of possibly different shapes, enqueued as one batch
+ * (the paper's fused parallel loop over independent units, Sec. 4.2).
+ *   cubes[i]   in : x_i as for stap_doppler.
+ *   steers[i]  in : V_i[S_i][D_i].
+ *   powers[i]  out: power_i[P_i][S_i][R_i].
+ *   weights    out: NULL, or weights[i] = W_i[P_i][B_i][S_i][D_i] (each may be
+ *                   NULL).
+ *   info       out: NULL, or info[i] = info_i[P_i][B_i] (each may be NULL).
+ *   workspace  scratch device memory of at least stap_workspace_size() bytes,
+ *              256-byte aligned; its contents on entry are ignored.
+ * All problems must share precision and refine_steps. */
+stap_status stap_run(const stap_problem* probs, int32_t n_probs,
+                     const stap_cf32* const* cubes,
+                     const stap_cf32* const* steers, float* const* powers,
+                     stap_cf32* const* weights, int32_t* const* info,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Bytes of device workspace stap_run needs for these problems; 0 on invalid
+ * arguments. */
+size_t stap_workspace_size(const stap_problem* probs, int32_t n_probs);
+
+/* Validate one problem without touching the GPU (host-only check). */
+stap_status stap_check_problem(const stap_problem* prob);
+
+/* Static description of a status code. */
+const char* stap_status_string(stap_status status);
+
+/* Library version, "major.minor.patch". */
+const char* stap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAP_H */

@@ -1,0 +1,227 @@
+// Shared definitions of the gfx950 STAP kernels: problem dimensions, complex
+// helpers, MFMA vector types and compile-time twiddle tables.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stap.h"
+
+namespace stap {
+
+constexpr int kMaxDof = 192;
+constexpr int kMaxSteer = 64;
+constexpr int kMaxTdof = 4;
+constexpr int kMinPulse = 32;
+constexpr int kMaxPulse = 512;
+
+// Problem dimensions as the kernels see them (all derived on the host).
+struct Dims {
+  int C, P, R, T, B, S;
+  int D;   // T*C, degrees of freedom
+  int N;   // R/B, range cells per training block
+  int L;   // P-T+1, sub-CPI (window) length
+  float eps;
+  int prec, refine;
+  long long sc, sp;  // cube strides of channel and pulse (elements)
+};
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+struct cf {
+  float re, im;
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// ---------------------------------------------------------------------------
+// Compile-time twiddles exp(-2 pi i j / 64), j = 0..63, evaluated in double by
+// the compiler (Taylor series after reduction to [-pi, pi]) and rounded once
+// to float.  In-register FFTs of size M <= 64 read W_M^j = W_64^(j*64/M).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+struct Tw64 {
+  float c[64];
+  float s[64];
+};
+constexpr Tw64 make_tw64() {
+  Tw64 t{};
+  for (int j = 0; j < 64; ++j) {
+    int jj = j > 32 ? j - 64 : j;  // angle in [-pi, pi]
+    double a = 2.0 * kPi * jj / 64.0;
+    t.c[j] = (float)taylor_cos(a);
+    t.s[j] = (float)taylor_sin(a);
+  }
+  return t;
+}
+
+// Correctly rounded tables, evaluated by the compiler in double.
+//   Tw<P>:  exp(-2 pi i m / P) = c[m] - i s[m], m = 0..P-1 (exact octant
+//           reduction in integers, Taylor series on [0, pi/4]).
+//   Win<P>: symmetric Hann window of length L = P - T + 1 for T = 1..4,
+//           h[T-1][n] = sin^2(pi n / (L-1)) for n < L, 0 beyond.
+constexpr double taylor_sin_small(double x) {
+  double term = x, sum = x;
+  for (int n = 1; n < 16; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos_small(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 16; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi m / P
+constexpr void sincos_frac(long long m, long long P, double& c, double& s) {
+  long long q4 = ((4 * m) / P) % 4;
+  long long rem = (4 * m) % P;  // angle in quadrant = (pi/2) rem / P
+  double cc, ss;
+  if (2 * rem <= P) {
+    const double psi = (kPi / 2.0) * (double)rem / (double)P;
+    cc = taylor_cos_small(psi);
+    ss = taylor_sin_small(psi);
+  } else {
+    const double psi = (kPi / 2.0) * (double)(P - rem) / (double)P;
+    cc = taylor_sin_small(psi);
+    ss = taylor_cos_small(psi);
+  }
+  if (q4 == 0) { c = cc; s = ss; }
+  else if (q4 == 1) { c = -ss; s = cc; }
+  else if (q4 == 2) { c = -cc; s = -ss; }
+  else { c = ss; s = -cc; }
+}
+template <int P>
+struct TwTab {
+  float c[P];
+  float s[P];
+};
+template <int P>
+constexpr TwTab<P> make_twtab() {
+  TwTab<P> t{};
+  for (int m = 0; m < P; ++m) {
+    double c = 0, s = 0;
+    sincos_frac(m, P, c, s);
+    t.c[m] = (float)c;
+    t.s[m] = (float)s;
+  }
+  return t;
+}
+template <int P>
+struct WinTab {
+  float h[4][P];
+};
+template <int P>
+constexpr WinTab<P> make_wintab() {
+  WinTab<P> w{};
+  for (int t = 0; t < 4; ++t) {
+    const int L = P - t;
+    for (int n = 0; n < P; ++n) {
+      double v = 0.0;
+      if (n < L && L > 1) {
+        // theta = pi n/(L-1) folded to [0, pi/2] with exact integer arithmetic
+        const int nn = (2 * n <= L - 1) ? n : (L - 1 - n);
+        double c = 0, s = 0;
+        sincos_frac(nn, 2LL * (L - 1), c, s);  // angle 2 pi nn / (2(L-1)) = pi nn/(L-1)
+        v = s * s;
+      }
+      w.h[t][n] = (float)v;
+    }
+  }
+  return w;
+}
+template <int P>
+__device__ const TwTab<P> kTwTab = make_twtab<P>();
+template <int P>
+__device__ const WinTab<P> kWinTab = make_wintab<P>();
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// Forward DFT of M points held in registers, natural order in and out:
+// v[k] <- sum_n v[n] exp(-2 pi i k n / M).  Radix-2 decimation in time; all
+// indices and twiddles are compile-time constants after unrolling.
+template <int M>
+__device__ __forceinline__ void fft_inreg(float2 (&v)[M]) {
+  constexpr int LOG = ilog2(M);
+  constexpr Tw64 tw = make_tw64();
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const int j = bitrev(i, LOG);
+    if (j > i) {
+      float2 t = v[i];
+      v[i] = v[j];
+      v[j] = t;
+    }
+  }
+#pragma unroll
+  for (int half = 1; half < M; half *= 2) {
+#pragma unroll
+    for (int start = 0; start < M; start += 2 * half) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int idx = j * (64 / (2 * half));
+        const float2 w = make_float2(tw.c[idx], -tw.s[idx]);
+        const float2 a = v[start + j];
+        const float2 b = (j == 0) ? v[start + j + half] : cmul(v[start + j + half], w);
+        v[start + j] = cadd(a, b);
+        v[start + j + half] = csub(a, b);
+      }
+    }
+  }
+}
+
+// Round-to-nearest-even float -> bf16 bits, and back.
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+// Split x into three bf16 terms with x = h + m + l to about 24 bits: each
+// residual is exact in FP32, so h*h' etc. are exact products in FP32.
+__device__ __forceinline__ void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
+  h = f2bf(x);
+  float r1 = x - bf2f(h);
+  m = f2bf(r1);
+  float r2 = r1 - bf2f(m);
+  l = f2bf(r2);
+}
+
+}  // namespace stap

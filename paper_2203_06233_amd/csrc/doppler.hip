@@ -1,0 +1,108 @@
+// Doppler filtering with time-staggered DOF (statements S and T of the STAP
+// kernel, Sec. 4.2; Table 2 row fft_{2D,axis=1}).
+//
+//   X[k][t*C+c][r] = sum_p h[p-t] x[c][p][r] exp(-2 pi i k p / P)
+//
+// One workgroup takes one channel c and RT consecutive range cells.  The
+// length-P DFT is split as P = P1 * P2 (p = P2*n1 + n2, k = k1 + P1*k2):
+//   pass 1  each thread owns one (n2, cell) and keeps the P1 samples
+//           x[P2*n1 + n2], n1 = 0..P1-1, in registers (loaded once, coalesced
+//           along range), windows them for tap t, runs a P1-point DFT in
+//           registers and multiplies by exp(-2 pi i k1 n2 / P);
+//   LDS     one transpose through a [k1][n2][cell] tile;
+//   pass 2  each (k1, cell) runs a P2-point DFT in registers and stores bins
+//           k1 + P1*k2 straight to X[k][d][r] (range fastest, coalesced).
+// The cube is read from HBM once for all T taps.  Twiddles of the inner DFTs
+// are compile-time constants; the P-point twiddles and the Hann window come
+// from correctly rounded compile-time tables, staged once per workgroup in LDS.
+#include "common.h"
+#include "kernels.h"
+
+namespace stap {
+
+template <int P>
+struct FftShape {
+  static constexpr int LOG = ilog2(P);
+  static constexpr int P1 = 1 << ((LOG + 1) / 2);
+  static constexpr int P2 = P / P1;
+  static constexpr int RT = 256 / P2;  // range cells per workgroup
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__ cube,
+                                                      float2* __restrict__ snap, Dims d) {
+  using Sh = FftShape<P>;
+  constexpr int P1 = Sh::P1, P2 = Sh::P2, RT = Sh::RT;
+  __shared__ float2 ybuf[P1 * P2 * RT];  // [k1][n2][cell]
+  __shared__ float2 tw[P];
+  __shared__ float hwin[P];
+
+  const int tid = threadIdx.x;
+  const int c = blockIdx.y;
+  const int r0 = blockIdx.x * RT;
+
+  for (int m = tid; m < P; m += 256) {
+    tw[m] = make_float2(kTwTab<P>.c[m], -kTwTab<P>.s[m]);
+    hwin[m] = kWinTab<P>.h[d.T - 1][m];
+  }
+
+  const int col = tid % RT, n2 = tid / RT;
+  const int r = r0 + col;
+  const bool live = r < d.R;
+  float2 x[P1];
+  const float2* src = cube + (long long)c * d.sc + r;
+#pragma unroll
+  for (int n1 = 0; n1 < P1; ++n1)
+    x[n1] = live ? src[(long long)(P2 * n1 + n2) * d.sp] : make_float2(0.f, 0.f);
+  __syncthreads();
+
+  for (int t = 0; t < d.T; ++t) {
+    float2 v[P1];
+#pragma unroll
+    for (int n1 = 0; n1 < P1; ++n1) {
+      const int q = P2 * n1 + n2 - t;
+      const float h = (q >= 0) ? hwin[q] : 0.f;
+      v[n1] = make_float2(x[n1].x * h, x[n1].y * h);
+    }
+    fft_inreg<P1>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < P1; ++k1) {
+      const float2 y = (k1 == 0) ? v[k1] : cmul(v[k1], tw[k1 * n2]);
+      ybuf[(k1 * P2 + n2) * RT + col] = y;
+    }
+    __syncthreads();
+    const int dof = t * d.C + c;
+    for (int task = tid; task < P1 * RT; task += 256) {
+      const int c3 = task % RT, k1 = task / RT;
+      float2 z[P2];
+#pragma unroll
+      for (int m2 = 0; m2 < P2; ++m2) z[m2] = ybuf[(k1 * P2 + m2) * RT + c3];
+      fft_inreg<P2>(z);
+      const int r3 = r0 + c3;
+      if (r3 < d.R) {
+        float2* dst = snap + (long long)dof * d.R + r3;
+#pragma unroll
+        for (int k2 = 0; k2 < P2; ++k2) dst[(long long)(k1 + P1 * k2) * d.D * d.R] = z[k2];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipStream_t st) {
+  auto go = [&](auto kern, int rt) {
+    dim3 grid((d.R + rt - 1) / rt, d.C);
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, cube, snap, d);
+    return hipGetLastError();
+  };
+  switch (d.P) {
+    case 32: return go(doppler_kernel<32>, FftShape<32>::RT);
+    case 64: return go(doppler_kernel<64>, FftShape<64>::RT);
+    case 128: return go(doppler_kernel<128>, FftShape<128>::RT);
+    case 256: return go(doppler_kernel<256>, FftShape<256>::RT);
+    case 512: return go(doppler_kernel<512>, FftShape<512>::RT);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace stap

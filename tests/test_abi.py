@@ -1,0 +1,132 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/stap.h, and rejects invalid requests on the host before
+any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stap.h")
+LIB = os.path.join(ROOT, "paper_2203_06233_amd", "libstap.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(stap_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not os.path.exists(LIB):
+        from paper_2203_06233_amd import build
+        build.build()
+    from paper_2203_06233_amd import stap
+    return stap
+
+
+def test_header_declares_the_five_entry_points():
+    names = _declared()
+    for n in ("stap_doppler", "stap_covariance", "stap_solve_weights", "stap_inner_products", "stap_run"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(binding):
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_and_version(binding):
+    assert binding.version().count(".") == 2
+    for code in range(-6, 1):
+        assert binding._string(code) != "unknown status"
+    assert binding._string(-99) == "unknown status"
+
+
+GOOD = dict(n_chan=4, n_pulse=64, n_range=512, tdof=3, n_block=32, n_steer=8)
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(n_pulse=48), -2), (dict(n_pulse=1024), -2), (dict(n_pulse=16), -2),
+    (dict(n_range=500), -2), (dict(n_range=0), -2), (dict(n_block=0), -2),
+    (dict(tdof=0), -2), (dict(tdof=5), -2), (dict(n_chan=65), -2),
+    (dict(n_steer=0), -2), (dict(n_steer=65), -2),
+    (dict(load_eps=-1.0), -1), (dict(load_eps=float("nan")), -1),
+    (dict(precision="fp32", refine_steps=5), -1),
+    (dict(cube_stride_pulse=100), -2),
+])
+def test_problem_validation(binding, change, code):
+    kw = dict(GOOD)
+    kw.update(change)
+    p = binding.problem(**kw)
+    assert binding._lib.stap_check_problem(ctypes.byref(p)) == code
+
+
+def test_valid_problems(binding):
+    for kw in (GOOD, dict(n_chan=32, n_pulse=256, n_range=16384, tdof=3, n_block=128, n_steer=32),
+               dict(n_chan=64, n_pulse=512, n_range=32768, tdof=3, n_block=256, n_steer=64),
+               dict(n_chan=5, n_pulse=32, n_range=7, tdof=1, n_block=7, n_steer=1)):
+        binding.check_problem(binding.problem(**kw))
+
+
+def test_bad_precision_code(binding):
+    p = binding.problem(**GOOD)
+    p.precision = 7
+    assert binding._lib.stap_check_problem(ctypes.byref(p)) == -1
+    p.precision = 0
+    p.reserved = 1
+    assert binding._lib.stap_check_problem(ctypes.byref(p)) == -1
+
+
+def test_entry_points_reject_before_touching_the_device(binding):
+    """Null or misaligned pointers and bad shapes return without a HIP call,
+    so these work on a machine with no GPU."""
+    lib = binding._lib
+    p = binding.problem(**GOOD)
+    bp = ctypes.byref(p)
+    fake = ctypes.c_void_p(0x10000)
+    odd = ctypes.c_void_p(0x10004)
+    assert lib.stap_doppler(bp, None, fake, None) == -1
+    assert lib.stap_doppler(bp, fake, None, None) == -1
+    assert lib.stap_doppler(bp, odd, fake, None) == -3
+    assert lib.stap_covariance(bp, fake, None, None, None) == -1
+    assert lib.stap_covariance(bp, fake, fake, ctypes.c_void_p(0x10002), None) == -3
+    assert lib.stap_solve_weights(bp, fake, fake, fake, None, None) == -1
+    assert lib.stap_inner_products(bp, fake, fake, None, None, None) == -1
+    bad = binding.problem(**dict(GOOD, n_range=500))
+    assert lib.stap_doppler(ctypes.byref(bad), fake, fake, None) == -2
+    # D > 128 is valid for the Doppler and covariance stages but not the solve
+    big = binding.problem(n_chan=64, n_pulse=512, n_range=32768, tdof=3, n_block=256, n_steer=64)
+    assert lib.stap_solve_weights(ctypes.byref(big), fake, fake, fake, fake, None) == -6
+
+
+def test_run_rejects_before_touching_the_device(binding):
+    lib = binding._lib
+    probs = (binding.Problem * 2)(binding.problem(**GOOD), binding.problem(**GOOD))
+    VP = ctypes.c_void_p * 2
+    fake = VP(0x10000, 0x20000)
+    need = lib.stap_workspace_size(probs, 2)
+    assert need > 0
+    # workspace too small
+    assert lib.stap_run(probs, 2, fake, fake, fake, None, None, ctypes.c_void_p(0x100000), need - 1, None) == -4
+    assert lib.stap_run(probs, 2, fake, fake, fake, None, None, None, need, None) == -4
+    # workspace misaligned
+    assert lib.stap_run(probs, 2, fake, fake, fake, None, None, ctypes.c_void_p(0x100010), need, None) == -3
+    # mixed precision across the batch
+    probs[1].precision = 1
+    assert lib.stap_run(probs, 2, fake, fake, fake, None, None, ctypes.c_void_p(0x100000), need, None) == -1
+    assert lib.stap_run(probs, 0, fake, fake, fake, None, None, ctypes.c_void_p(0x100000), need, None) == -1
+
+
+def test_workspace_size_formula(binding):
+    p = binding.problem(**GOOD)
+    P, D, R, B, S = 64, 12, 512, 32, 8
+
+    def up(x):
+        return (x + 255) // 256 * 256
+    want = up(P * D * R * 8) + up(P * B * D * D * 8) + up(P * B * 4) + up(P * B * S * D * 8) + up(P * B * 4)
+    assert binding.workspace_size([p]) == want
+    assert binding.workspace_size([p, p]) == 2 * want

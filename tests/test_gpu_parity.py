@@ -1,0 +1,342 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Stage tests feed each kernel the oracle's own intermediate, rounded to
+complex64, and compare with the oracle's FP64 result on that same rounded
+input, element by element, against bounds derived from FP32 arithmetic.
+Chain tests run ``stap_run`` on seeded cubes and compare with the oracle run
+on the same cube: output power normwise <= 1e-4 on the plain FP32 path;
+weights <= 1e-3 and SINR loss <= 0.1 dB on the mixed BF16 path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import metrics
+from oracle import stap as orc
+from tests.gpu_common import U32, binding, dev, fft_bound, host, prob_of
+
+pytestmark = pytest.mark.gpu
+
+# (C, P, R, T, B, S): ragged range tiles, D and S off multiples of 16, T = 1
+# and 4, P = 32 and 512, N = 1, odd N.
+TINY = [
+    (2, 32, 40, 3, 5, 3),
+    (5, 64, 99, 3, 3, 17),
+    (3, 128, 70, 1, 2, 5),
+    (4, 512, 33, 4, 1, 16),
+    (16, 256, 64, 2, 1, 9),
+    (8, 64, 24, 3, 24, 4),
+]
+
+
+def tiny_wl(shape, seed=7):
+    C, P, R, T, B, S = shape
+    return synth.Workload(f"tiny-{C}-{P}-{R}-{T}-{B}-{S}", C, P, R, T, B, S, cnr_db=30.0, seed=seed)
+
+
+@pytest.fixture(scope="module")
+def stap():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return binding()
+
+
+def _report(tag, **vals):
+    print(tag, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}" for k, v in vals.items()),
+          flush=True)
+
+
+# ------------------------------------------------------------------ Doppler
+
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8)], ids=str)
+def test_doppler_parity(stap, shape):
+    wl = tiny_wl(shape)
+    cube = synth.make_cube(wl)
+    prob = prob_of(wl)
+    X = host(stap.doppler(prob, dev(cube)))
+    Xo = orc.doppler(cube, wl.tdof)
+    err = np.abs(X - Xo)
+    bnd = fft_bound(cube, wl.tdof)
+    _report("doppler", shape=shape, max_ratio=float((err / bnd).max()), rel=metrics.rel_err(X, Xo))
+    assert np.all(err <= bnd)
+
+
+def test_doppler_strided_cube(stap):
+    wl = tiny_wl((3, 64, 50, 3, 5, 4))
+    cube = synth.make_cube(wl)
+    big = np.zeros((3, 64, 64), np.complex64)
+    big[:, :, :50] = cube
+    prob = prob_of(wl, cube_stride_pulse=64, cube_stride_chan=64 * 64)
+    X1 = host(stap.doppler(prob, dev(big)))
+    X0 = host(stap.doppler(prob_of(wl), dev(cube)))
+    assert np.array_equal(X0, X1)
+
+
+# ---------------------------------------------------------------- covariance
+
+def _cov_case(wl):
+    cube = synth.make_cube(wl)
+    X32 = orc.doppler(cube, wl.tdof).astype(np.complex64)
+    Rh = orc.covariance(X32.astype(np.complex128), wl.n_block)
+    delta, RL = orc.loading(Rh, wl.load_eps)
+    return X32, Rh, delta, RL
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 512, 3, 8, 16)], ids=str)
+def test_covariance_parity(stap, shape, precision):
+    wl = tiny_wl(shape)
+    X32, Rh, delta_o, RL = _cov_case(wl)
+    prob = prob_of(wl, precision)
+    cov, delta = stap.covariance(prob, dev(X32))
+    cov, delta = host(cov), host(delta)
+    # bitwise Hermitian, real diagonal
+    assert np.array_equal(cov, np.conj(cov.swapaxes(-1, -2)))
+    assert np.all(np.diagonal(cov, axis1=-2, axis2=-1).imag == 0)
+    dg = np.real(np.diagonal(Rh, axis1=-2, axis2=-1))
+    N = wl.n_cell
+    bnd = 4.0 * (N + 4) * U32 * np.sqrt(dg[..., :, None] * dg[..., None, :])
+    bnd = bnd + 4.0 * U32 * delta_o[..., None, None] * np.eye(wl.dof)
+    err = np.abs(cov - RL)
+    _report("cov", shape=shape, prec=precision, max_ratio=float((err / bnd).max()), rel=metrics.rel_err(cov, RL))
+    assert np.all(err <= bnd)
+    # delta = eps tr / D inherits the diagonal's accumulation error
+    assert np.all(np.abs(delta - delta_o) <= 4.0 * (N + 4) * U32 * delta_o + 1e-30)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
+def test_covariance_exact_integers(stap, precision):
+    """Integer snapshots with |Re|, |Im| <= 8: every product and partial sum
+    is exact in FP32, BF16 and E4M3 (after the power-of-two scale), so the
+    covariance off the diagonal is bitwise the exact value (eps = 0)."""
+    rng = np.random.default_rng(11)
+    P = 32
+    for (D, N, B) in [(12, 16, 3), (48, 64, 2), (96, 128, 1), (17, 33, 2)]:
+        X = (rng.integers(-8, 9, (P, D, N * B)) + 1j * rng.integers(-8, 9, (P, D, N * B))).astype(np.complex64)
+        X[:, 0, :] = 8  # every system's largest component is 8: FP8 scale 2^4
+        prob = binding().problem(D, P, N * B, 1, B, 1, load_eps=0.0, precision=precision)
+        cov, delta = stap.covariance(prob, dev(X))
+        cov, delta = host(cov), host(delta)
+        want = orc.covariance(X.astype(np.complex128), B)
+        assert np.array_equal(cov, want.astype(np.complex64)), (precision, D, N)
+        assert np.all(delta == 0)
+
+
+def test_covariance_fp8_error_reported(stap):
+    wl = tiny_wl((16, 128, 512, 3, 4, 16))
+    X32, Rh, delta_o, RL = _cov_case(wl)
+    cov, _ = stap.covariance(prob_of(wl, "fp8"), dev(X32))
+    cov = host(cov)
+    rel = metrics.rel_err(cov, RL)
+    _report("cov fp8", rel=rel)
+    assert rel < 0.2  # E4M3 keeps 3 mantissa bits; the error is reported, not pinned
+
+
+# -------------------------------------------------------------------- solve
+
+def _solve_case(wl):
+    X32, Rh, delta, RL = _cov_case(wl)
+    RL32 = RL.astype(np.complex64)
+    V = synth.steering(wl)
+    Wo, Go, Io = orc.solve_weights(RL32.astype(np.complex128), V)
+    return RL32, V, Wo, Go, Io
+
+
+@pytest.mark.parametrize("refine", [0, 1, 2])
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 1024, 3, 16, 16),
+                                          (32, 32, 256, 3, 2, 32), (32, 32, 256, 3, 2, 64),
+                                          (40, 32, 256, 3, 2, 20)], ids=str)
+def test_solve_parity(stap, shape, refine):
+    wl = tiny_wl(shape)
+    RL32, V, Wo, Go, Io = _solve_case(wl)
+    w, info = stap.solve_weights(prob_of(wl, refine=refine), dev(RL32), dev(V))
+    w, info = host(w), host(info)
+    assert np.all(info == Io)
+    ok = Io == 0
+    cond = np.linalg.cond(RL32.astype(np.complex128))
+    per = metrics.per_system_rel_err(w, Wo)
+    bnd = 8.0 * wl.dof * cond * U32
+    _report("solve", shape=shape, refine=refine, rel=metrics.rel_err(w, Wo),
+            max_ratio=float((per / bnd)[ok].max()), cond=float(cond.max()))
+    assert np.all(per[ok] <= bnd[ok])
+    # backward error of the solve, recovered from w: gamma = (v^H w)^2, u = w sqrt(gamma)
+    vw = np.real(np.einsum("sd,...sd->...s", np.conj(V.astype(np.complex128)), w.astype(np.complex128)))
+    u = w.astype(np.complex128) * vw[..., None]
+    R = RL32.astype(np.complex128)
+    res = np.einsum("...ij,...sj->...si", R, u) - V[None, None]
+    nrm = np.linalg.norm(res, axis=-1) / (np.linalg.norm(R, 2, axis=(-2, -1))[..., None] * np.linalg.norm(u, axis=-1))
+    assert np.all(nrm[ok] <= 8.0 * wl.dof * U32)
+
+
+def test_refinement_reduces_solve_error(stap):
+    wl = tiny_wl((16, 128, 1024, 3, 16, 16))
+    RL32, V, Wo, Go, Io = _solve_case(wl)
+    errs = []
+    for refine in (0, 1, 2):
+        w, _ = stap.solve_weights(prob_of(wl, refine=refine), dev(RL32), dev(V))
+        errs.append(metrics.rel_err(host(w), Wo))
+    _report("refine", e0=errs[0], e1=errs[1], e2=errs[2])
+    assert errs[1] <= 0.5 * errs[0] + 2e-7
+    assert errs[2] <= errs[1] + 2e-7
+
+
+def test_solve_info_codes(stap):
+    D, S, P = 20, 5, 32
+    mats, want = [], []
+    for j in (0, 3, 17, 19):
+        A = np.eye(D, dtype=np.complex64)
+        A[j, j] = -1.0
+        mats.append(A)
+        want.append(j + 1)
+    A = np.eye(D, dtype=np.complex64)
+    A[4, 5] = A[5, 4] = 2.0  # [[1, 2], [2, 1]]: the second pivot is 1 - 4 < 0
+    mats.append(A)
+    want.append(6)
+    while len(mats) < P:
+        mats.append(2.0 * np.eye(D, dtype=np.complex64))
+        want.append(0)
+    cov = np.stack(mats)[:, None]  # [P][B=1][D][D]
+    V = np.exp(2j * np.pi * np.random.default_rng(3).random((S, D))).astype(np.complex64)
+    prob = binding().problem(D // 4, P, 32, 4, 1, S)  # D = 4 * 5 = 20
+    w, info = stap.solve_weights(prob, dev(cov), dev(V))
+    w, info = host(w), host(info)
+    assert list(info[:, 0]) == want
+    assert np.all(w[np.array(want) > 0] == 0)
+    # R = 2 I: u = v / 2, gamma = ||v||^2 / 2, w = v / (sqrt(2) ||v||)
+    want = V / (np.sqrt(2.0) * np.linalg.norm(V, axis=1)[:, None])
+    np.testing.assert_allclose(w[-1, 0], want, rtol=0, atol=1e-6 * np.abs(want).max())
+
+
+def test_white_snapshots_give_steering_weights(stap):
+    """R_hat = sigma^2 I exactly (rows of a unitary DFT) through the covariance
+    and solve kernels: w = v / (sigma sqrt(1+eps) ||v||)."""
+    D, N, S, eps, sigma, P = 12, 16, 8, 1e-3, 1.5, 32
+    F = np.exp(-2j * np.pi * np.outer(np.arange(N), np.arange(N)) / N) / np.sqrt(N)
+    X = np.broadcast_to(sigma * np.sqrt(N) * F[:D], (P, D, N)).astype(np.complex64)
+    V = synth.steering(synth.SMALL)  # [8][12]
+    for precision in ("fp32", "bf16"):
+        prob = binding().problem(4, P, N, 3, 1, S, load_eps=eps, precision=precision)
+        cov, _ = stap.covariance(prob, dev(X))
+        w, info = stap.solve_weights(prob, cov, dev(V))
+        w, info = host(w), host(info)
+        assert np.all(info == 0)
+        want = V / (sigma * np.sqrt(1 + eps) * np.linalg.norm(V, axis=1)[:, None])
+        for k in range(P):
+            np.testing.assert_allclose(w[k, 0], want, rtol=0, atol=2e-6 * np.abs(want).max())
+
+
+# ------------------------------------------------------------ inner products
+
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (32, 32, 256, 3, 2, 64)], ids=str)
+def test_inner_parity(stap, shape):
+    wl = tiny_wl(shape)
+    cube = synth.make_cube(wl)
+    X32 = orc.doppler(cube, wl.tdof).astype(np.complex64)
+    o = orc.run_from_snapshots(X32.astype(np.complex128), synth.steering(wl), wl.n_block, wl.load_eps)
+    W32 = o["W"].astype(np.complex64)
+    yo, po = orc.inner_products(W32.astype(np.complex128), X32.astype(np.complex128), wl.n_block)
+    power, y = stap.inner_products(prob_of(wl), dev(W32), dev(X32), want_y=True)
+    power, y = host(power), host(y)
+    P, D, R = X32.shape
+    N = wl.n_cell
+    absW = np.abs(W32.astype(np.complex128))
+    absX = np.abs(X32.astype(np.complex128)).reshape(P, D, wl.n_block, N).transpose(0, 2, 1, 3)
+    l1 = (absW @ absX).transpose(0, 2, 1, 3).reshape(P, wl.n_steer, R)  # sum_d |w||x|
+    dy = 4.0 * (D + 2) * U32 * l1
+    assert np.all(np.abs(y - yo) <= dy)
+    bp = 2 * np.abs(yo) * dy + dy ** 2 + 2 * U32 * po
+    _report("inner", shape=shape, max_ratio=float((np.abs(power - po) / bp).max()))
+    assert np.all(np.abs(power - po) <= bp)
+
+
+# ------------------------------------------------------------- whole chain
+
+def _run_gpu(stap, wl, precision, refine=0):
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    prob = prob_of(wl, precision, refine)
+    W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
+    info = torch.empty((wl.n_pulse, wl.n_block), dtype=torch.int32, device="cuda")
+    power = stap.run([prob], [dev(cube)], [dev(V)], weights=[W], info=[info])[0]
+    return cube, V, host(power), host(W), host(info)
+
+
+@pytest.mark.parametrize("wl", [synth.SMALL, synth.MEDIUM], ids=lambda w: w.name)
+def test_chain_plain_fp32(stap, wl):
+    cube, V, power, W, info = _run_gpu(stap, wl, "fp32")
+    o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+    assert np.all(info == 0)
+    pe = metrics.rel_err(power, o["power"])
+    we = metrics.rel_err(W, o["W"])
+    sl = metrics.sinr_loss_db(W, o["W"], V, o["R_L"])
+    _report("chain fp32", wl=wl.name, power=pe, weights=we, sinr_max=float(sl.max()))
+    assert pe <= 1e-4
+    sc = synth.scene(wl)
+    k, s, r = np.unravel_index(int(np.argmax(power)), power.shape)
+    assert (s, r) == (sc.target_steer, sc.target_cell)
+    assert min((k - sc.target_bin) % wl.n_pulse, (sc.target_bin - k) % wl.n_pulse) <= 1
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+@pytest.mark.parametrize("wl", [synth.SMALL, synth.MEDIUM], ids=lambda w: w.name)
+def test_chain_mixed_bf16(stap, wl, refine):
+    cube, V, power, W, info = _run_gpu(stap, wl, "bf16", refine)
+    o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+    assert np.all(info == 0)
+    we = metrics.rel_err(W, o["W"])
+    sl = metrics.sinr_loss_db(W, o["W"], V, o["R_L"])
+    pe = metrics.rel_err(power, o["power"])
+    _report("chain bf16", wl=wl.name, refine=refine, weights=we,
+            weights_sys_max=float(metrics.per_system_rel_err(W, o["W"]).max()),
+            sinr_max=float(sl.max()), sinr_mean=float(sl.mean()), power=pe)
+    assert we <= 1e-3
+    assert sl.max() <= 0.1
+
+
+@pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 1)])
+def test_chain_large_sampled(stap, precision, refine):
+    """The full-size mixed-precision workload on the GPU; the oracle recomputes
+    three training blocks (all Doppler bins) from their own cube cells."""
+    wl = synth.LARGE
+    cube, V, power, W, info = _run_gpu(stap, wl, precision, refine)
+    assert np.all(info == 0)
+    assert np.all(np.isfinite(power))
+    N = wl.n_cell
+    for b in (0, 61, wl.n_block - 1):
+        ob = orc.run_block(cube[:, :, b * N:(b + 1) * N], V, wl.tdof, wl.load_eps)
+        Wb = W[:, b]
+        pb = power[:, :, b * N:(b + 1) * N]
+        we = metrics.rel_err(Wb, ob["W"][:, 0])
+        pe = metrics.rel_err(pb, ob["power"])
+        sl = metrics.sinr_loss_db(Wb, ob["W"][:, 0], V, ob["R_L"][:, 0])
+        _report("large", prec=precision, block=b, weights=we, power=pe, sinr_max=float(sl.max()))
+        assert we <= 1e-3
+        assert sl.max() <= 0.1
+        if precision == "fp32":
+            assert pe <= 1e-4
+
+
+def test_stages_equal_run_and_deterministic(stap):
+    wl = synth.SMALL
+    cube = dev(synth.make_cube(wl))
+    V = dev(synth.steering(wl))
+    prob = prob_of(wl, "bf16", 1)
+    X = stap.doppler(prob, cube)
+    cov, _ = stap.covariance(prob, X)
+    w, info = stap.solve_weights(prob, cov, V)
+    p_stage = host(stap.inner_products(prob, w, X))
+    p1 = host(stap.run([prob], [cube], [V])[0])
+    p2 = host(stap.run([prob], [cube], [V])[0])
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(p_stage, p1)
+
+
+def test_batched_run_equals_single(stap):
+    wls = synth.uneven_batch(4)
+    cubes = [dev(synth.make_cube(w)) for w in wls]
+    Vs = [dev(synth.steering(w)) for w in wls]
+    probs = [prob_of(w, "bf16", 1) for w in wls]
+    batched = [host(p) for p in stap.run(probs, cubes, Vs)]
+    for i in range(len(wls)):
+        single = host(stap.run([probs[i]], [cubes[i]], [Vs[i]])[0])
+        assert np.array_equal(batched[i], single)
