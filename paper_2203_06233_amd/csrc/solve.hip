@@ -34,7 +34,7 @@ struct SolveShape {
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-template <int NB, int NV>
+template <int NB, int NV, bool REFINE>
 __global__ __launch_bounds__(256) void solve_kernel(const float2* __restrict__ cov,
                                                     const float2* __restrict__ steer,
                                                     float2* __restrict__ wout, int* __restrict__ info_out,
@@ -50,12 +50,12 @@ __global__ __launch_bounds__(256) void solve_kernel(const float2* __restrict__ c
   const int sys = blockIdx.x;
   const int D = d.D, S = d.S;
   const float2* A = cov + (long long)sys * D * D;
-  const int refine = d.refine;
+  const int refine = REFINE ? d.refine : 0;
 
   float2 lm[NB][NB];
   float2 vm[NV][NB];
 
-  if (refine > 0) {
+  if (REFINE) {
     // stage the lower triangle packed: row i at i(i+1)/2
     float2* Rp = dyn;
     for (int i = ty; i < D; i += 16)
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void solve_kernel(const float2* __restrict__ c
 
   back_solve(vm);
 
-  if (refine > 0) {
+  if (REFINE) {
     const float2* Rp = dyn;
     float2* ub = dyn + DP * (DP + 1) / 2;  // [SP][DP] conj(u)
     for (int it = 0; it < refine; ++it) {
@@ -374,13 +374,15 @@ __global__ __launch_bounds__(256) void solve_kernel(const float2* __restrict__ c
 template <int NB, int NV>
 hipError_t go_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                     hipStream_t st) {
-  const size_t dyn = SolveShape<NB, NV>::dyn_lds(d.refine);
-  if (dyn > 0) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&solve_kernel<NB, NV>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-    if (e != hipSuccess) return e;
+  if (d.refine == 0) {
+    hipLaunchKernelGGL((solve_kernel<NB, NV, false>), dim3(d.P * d.B), dim3(256), 0, st, cov, steer, w, info, d);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL((solve_kernel<NB, NV>), dim3(d.P * d.B), dim3(256), dyn, st, cov, steer, w, info, d);
+  const size_t dyn = SolveShape<NB, NV>::dyn_lds(d.refine);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&solve_kernel<NB, NV, true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((solve_kernel<NB, NV, true>), dim3(d.P * d.B), dim3(256), dyn, st, cov, steer, w, info, d);
   return hipGetLastError();
 }
 
