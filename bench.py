@@ -74,6 +74,9 @@ def kernel_work(wl, precision, refine):
         "doppler": dict(bytes=cube_b + snap_b, fp32=5.0 * T * C * R * P * np.log2(P)),
         "covariance": {"bytes": snap_b + cov_b, cov_key: herm},
         "solve": dict(bytes=cov_lower_b + w_b, fp32=chol + solves * (1 + refine), fp64=solves * refine),
+        # fused: snapshots in, weights out; covariance products plus the solve
+        "covariance_solve": {"bytes": snap_b + w_b, cov_key: herm,
+                             "fp32": chol + solves * (1 + refine), "fp64": solves * refine},
         "inner": dict(bytes=snap_b + w_b + pw_b, fp32=8.0 * S * D * N * sysn),
     }
 
@@ -170,14 +173,13 @@ def main():
         w = wls[0]
         prob = mkprob(w, args.precision, args.refine)
         st = torch.cuda.current_stream()
+        # the kernels stap_run launches: Doppler, fused covariance->solve, inner
         snap = stap.doppler(prob, cubes[0])
-        cov, delta = stap.covariance(prob, snap)
-        wts, inf = stap.solve_weights(prob, cov, steers[0])
+        wts, inf = stap.covariance_solve(prob, snap, steers[0])
         pwr = stap.inner_products(prob, wts, snap)
         calls = {
             "doppler": lambda: stap.doppler(prob, cubes[0], snap),
-            "covariance": lambda: stap.covariance(prob, snap, cov, delta),
-            "solve": lambda: stap.solve_weights(prob, cov, steers[0], wts, inf),
+            "covariance_solve": lambda: stap.covariance_solve(prob, snap, steers[0], wts, inf),
             "inner": lambda: stap.inner_products(prob, wts, snap, pwr),
         }
         work = kernel_work(w, args.precision, args.refine)
@@ -196,7 +198,7 @@ def main():
         r = kern[dom]
         roof = dict(kernel=dom, bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
                     frac=r["frac"], traffic=None)
-        del snap, cov, delta, wts, inf, pwr
+        del snap, wts, inf, pwr
 
     # accuracy against the FP64 oracle on sampled training blocks
     from oracle import metrics

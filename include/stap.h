@@ -31,7 +31,8 @@
  *   - Complex values are stap_cf32 {re, im} (bit-compatible with
  *     std::complex<float>, numpy complex64 and torch.complex64).
  *   - Arrays are dense, row-major, last index fastest, in the layouts given
- *     with each argument.  Device pointers must be 16-byte aligned
+ *     with each argument.  Complex arrays must be 8-byte aligned, float and
+ *     int32 arrays 4-byte aligned, the stap_run workspace 256-byte aligned
  *     (STAP_ERR_ALIGN otherwise).
  *   - Argument, shape, alignment and workspace errors are detected on the
  *     host before anything is enqueued and return a negative stap_status.
@@ -61,7 +62,7 @@ typedef enum stap_status {
   STAP_OK = 0,
   STAP_ERR_ARG = -1,          /* null pointer or value out of range */
   STAP_ERR_SHAPE = -2,        /* dimensions outside the supported limits */
-  STAP_ERR_ALIGN = -3,        /* a device pointer is not 16-byte aligned */
+  STAP_ERR_ALIGN = -3,        /* a device pointer is misaligned */
   STAP_ERR_WORKSPACE = -4,    /* workspace missing or smaller than needed */
   STAP_ERR_HIP = -5,          /* a HIP runtime call failed (launch, query) */
   STAP_ERR_UNSUPPORTED = -6   /* valid request this build does not handle */
@@ -128,6 +129,17 @@ stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov,
                                const stap_cf32* steer, stap_cf32* w,
                                int32_t* info, void* stream);
 
+/* Covariance, loading, Cholesky and solves fused per system (the path
+ * stap_run takes): the loaded covariance stays on chip.  Same definitions,
+ * arithmetic and outputs as stap_covariance followed by stap_solve_weights
+ * (weights and info; the covariance itself is not written).
+ *   snap  in : X[P][D][R];  steer in: V[S][D].
+ *   w     out: W[P][B][S][D];  info out: info[P][B].
+ * STAP_ERR_UNSUPPORTED for D > 128 or FP8 (use the two stage calls). */
+stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap,
+                                  const stap_cf32* steer, stap_cf32* w,
+                                  int32_t* info, void* stream);
+
 /* Weight x snapshot inner products and output power (statement U applied to
  * the weights; the adaptive filter output).
  *   w     in : W[P][B][S][D];  snap in: X[P][D][R].
@@ -148,12 +160,37 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
  *   info       out: NULL, or info[i] = info_i[P_i][B_i] (each may be NULL).
  *   workspace  scratch device memory of at least stap_workspace_size() bytes,
  *              256-byte aligned; its contents on entry are ignored.
- * All problems must share precision and refine_steps. */
+ * All problems must share precision and refine_steps.  With n_probs > 1 and
+ * every cube fused-eligible (D <= 128, FP32 or BF16) the batch runs as one
+ * Doppler launch per pulse count, one persistent covariance->solve launch
+ * over every (cube, bin, block) system ordered by cost, and one
+ * inner-product launch; the problem table (n_probs * 128 bytes) is copied
+ * from the host into the workspace and the launch chain is replayed from a
+ * cached hipGraph.  Calls that overlap on one workspace race. */
 stap_status stap_run(const stap_problem* probs, int32_t n_probs,
                      const stap_cf32* const* cubes,
                      const stap_cf32* const* steers, float* const* powers,
                      stap_cf32* const* weights, int32_t* const* info,
                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Kernel-variant selection, written by the autotuner (tune.py) and read by
+ * stap_run.  kind 0 = the fused covariance->solve kernel.  An entry applies to
+ * the shape class containing (dof, n_steer): dof classes end at
+ * 16, 32, 48, 64, 96, 128, 160, 192 and steering classes at 16, 32, 64.
+ * variant: 0 = built-in default, 16 or 32 = rows per register slot of the
+ * solve (a 16 x 16 or 32 x 16 thread grid per system).  Not thread-safe with
+ * respect to concurrent stap_run calls.  Returns STAP_ERR_ARG for values out
+ * of range. */
+stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine,
+                          int32_t variant);
+/* The variant stored for that class (0 = default), or -1 for invalid input. */
+int32_t stap_tune_get(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine);
+
+/* Whether stap_run replays a cached hipGraph of its batched launch chain
+ * (n_probs > 1; default on).  Off: the same kernels are launched directly.
+ * When the caller's stream is itself being captured the kernels are always
+ * launched directly into that capture. */
+void stap_use_graphs(int32_t enable);
 
 /* Bytes of device workspace stap_run needs for these problems; 0 on invalid
  * arguments. */

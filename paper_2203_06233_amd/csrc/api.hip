@@ -5,6 +5,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -58,29 +64,80 @@ Dims dims_of(const stap_problem* q) {
   return d;
 }
 
-// The register-resident solve handles D <= 128.
+// Every validated shape is solvable: D <= 128 on a 16 x 16 thread grid,
+// D <= 192 on a 32 x 16 grid.
 stap_status check_solvable(const stap_problem* q) {
-  return (q->tdof * q->n_chan > 128) ? STAP_ERR_UNSUPPORTED : STAP_OK;
+  return (q->tdof * q->n_chan > stap::kMaxDof) ? STAP_ERR_UNSUPPORTED : STAP_OK;
 }
 
 stap_status hip_status(hipError_t e) { return e == hipSuccess ? STAP_OK : STAP_ERR_HIP; }
 
+// Kernel-variant table written by the autotuner: [kind][dof class][steer
+// class][precision][refine] -> variant (0 = built-in default).
+constexpr int kDofClass[] = {16, 32, 48, 64, 96, 128, 160, 192};
+constexpr int kSteerClass[] = {16, 32, 64};
+int8_t g_tune[1][8][3][3][2];
+
+int dof_class(int d) {
+  for (int i = 0; i < 8; ++i)
+    if (d <= kDofClass[i]) return i;
+  return -1;
+}
+int steer_class(int s) {
+  for (int i = 0; i < 3; ++i)
+    if (s <= kSteerClass[i]) return i;
+  return -1;
+}
+int fused_variant(const Dims& d) {
+  const int dc = dof_class(d.D), sc = steer_class(d.S);
+  if (dc < 0 || sc < 0) return 16;
+  const int v = g_tune[0][dc][sc][d.prec][d.refine > 0 ? 1 : 0];
+  return v == 0 ? 16 : v;
+}
+
 constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Workspace of one cube: snapshots, weights and info (when the caller passes
+// none), and the covariance and delta only where the fused kernel does not
+// apply (D > 128 or FP8).
 struct Parts {
   size_t snap, cov, delta, w, info;
+  size_t total() const { return snap + cov + delta + w + info; }
 };
 Parts parts_of(const stap_problem* q) {
   const size_t P = q->n_pulse, D = (size_t)q->tdof * q->n_chan, R = q->n_range, B = q->n_block,
                S = q->n_steer;
+  const bool fused = stap::fused_supported(dims_of(q));
   Parts p;
   p.snap = up(P * D * R * 8);
-  p.cov = up(P * B * D * D * 8);
-  p.delta = up(P * B * 4);
+  p.cov = fused ? 0 : up(P * B * D * D * 8);
+  p.delta = fused ? 0 : up(P * B * 4);
   p.w = up(P * B * S * D * 8);
   p.info = up(P * B * 4);
   return p;
+}
+size_t table_bytes(int n) { return up((size_t)n * sizeof(stap::ProbDesc)); }
+
+// Per-system cost used to order a batch (largest first).
+double system_cost(const Dims& d) {
+  const double D = d.D, S = d.S, N = d.N;
+  return D * D * D / 3.0 + D * D * S + D * D * N / 2.0 + S * D * N;
+}
+
+bool g_use_graphs = true;
+
+// hipGraph cache of the batched chain, keyed by device, workspace address
+// and every launch parameter.  The graph's kernels read the problem table
+// from the workspace, so one graph serves every call with the same shapes.
+struct GraphCache {
+  std::mutex mu;
+  std::map<std::string, hipGraphExec_t> exec;
+  std::map<int, hipStream_t> capture_stream;
+};
+GraphCache& graphs() {
+  static GraphCache* g = new GraphCache();  // lives until the process ends
+  return *g;
 }
 
 }  // namespace
@@ -123,6 +180,18 @@ stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov, c
                                        info, (hipStream_t)stream));
 }
 
+stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap, const stap_cf32* steer,
+                                  stap_cf32* w, int32_t* info, void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!snap || !steer || !w || !info) return STAP_ERR_ARG;
+  if (!aligned(snap, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  if (!stap::fused_supported(d)) return STAP_ERR_UNSUPPORTED;
+  return hip_status(stap::launch_fused(d, reinterpret_cast<const float2*>(snap), reinterpret_cast<const float2*>(steer),
+                                       reinterpret_cast<float2*>(w), info, (hipStream_t)stream, fused_variant(d)));
+}
+
 stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w, const stap_cf32* snap,
                                 float* power, stap_cf32* y, void* stream) {
   stap_status s = check(prob);
@@ -137,11 +206,10 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w, co
 
 size_t stap_workspace_size(const stap_problem* probs, int32_t n_probs) {
   if (!probs || n_probs < 1) return 0;
-  size_t total = 0;
+  size_t total = table_bytes(n_probs);
   for (int i = 0; i < n_probs; ++i) {
     if (check(&probs[i]) != STAP_OK) return 0;
-    const Parts p = parts_of(&probs[i]);
-    total += p.snap + p.cov + p.delta + p.w + p.info;
+    total += parts_of(&probs[i]).total();
   }
   return total;
 }
@@ -166,31 +234,146 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
   if (!aligned(workspace, kAlign)) return STAP_ERR_ALIGN;
 
   hipStream_t st = (hipStream_t)stream;
-  char* ws = static_cast<char*>(workspace);
+  char* const ws0 = static_cast<char*>(workspace);
+  stap::ProbDesc* table = reinterpret_cast<stap::ProbDesc*>(ws0);
+  char* ws = ws0 + table_bytes(n_probs);
+  std::vector<stap::ProbDesc> desc(n_probs);
+  bool all_fused = true;
   for (int i = 0; i < n_probs; ++i) {
     const Dims d = dims_of(&probs[i]);
     const Parts p = parts_of(&probs[i]);
-    float2* snap = reinterpret_cast<float2*>(ws);
-    ws += p.snap;
-    float2* cov = reinterpret_cast<float2*>(ws);
-    ws += p.cov;
-    float* delta = reinterpret_cast<float*>(ws);
-    ws += p.delta;
-    float2* w = reinterpret_cast<float2*>(ws);
-    ws += p.w;
-    int* inf = reinterpret_cast<int*>(ws);
-    ws += p.info;
-    if (weights && weights[i]) w = reinterpret_cast<float2*>(weights[i]);
-    if (info && info[i]) inf = info[i];
-    hipError_t e = stap::launch_doppler(d, reinterpret_cast<const float2*>(cubes[i]), snap, st);
-    if (e == hipSuccess) e = stap::launch_covariance(d, snap, cov, delta, st);
-    if (e == hipSuccess)
-      e = stap::launch_solve(d, cov, reinterpret_cast<const float2*>(steers[i]), w, inf, st);
-    if (e == hipSuccess) e = stap::launch_inner(d, w, snap, powers[i], nullptr, st);
-    if (e != hipSuccess) return STAP_ERR_HIP;
+    stap::ProbDesc& pd = desc[i];
+    pd.d = d;
+    pd.cube = reinterpret_cast<const float2*>(cubes[i]);
+    pd.steer = reinterpret_cast<const float2*>(steers[i]);
+    pd.power = powers[i];
+    pd.snap = reinterpret_cast<float2*>(ws);
+    pd.w = reinterpret_cast<float2*>(ws + p.snap + p.cov + p.delta);
+    pd.info = reinterpret_cast<int*>(ws + p.snap + p.cov + p.delta + p.w);
+    ws += p.total();
+    if (weights && weights[i]) pd.w = reinterpret_cast<float2*>(weights[i]);
+    if (info && info[i]) pd.info = info[i];
+    pd.sys_begin = 0;
+    all_fused = all_fused && stap::fused_supported(d);
   }
-  return STAP_OK;
+
+  if (n_probs == 1 || !all_fused) {
+    char* wsp = ws0 + table_bytes(n_probs);
+    for (int i = 0; i < n_probs; ++i) {
+      const stap::ProbDesc& pd = desc[i];
+      const Dims& d = pd.d;
+      const Parts p = parts_of(&probs[i]);
+      float2* cov = reinterpret_cast<float2*>(wsp + p.snap);
+      float* delta = reinterpret_cast<float*>(wsp + p.snap + p.cov);
+      wsp += p.total();
+      hipError_t e = stap::launch_doppler(d, pd.cube, pd.snap, st);
+      if (stap::fused_supported(d)) {
+        if (e == hipSuccess) e = stap::launch_fused(d, pd.snap, pd.steer, pd.w, pd.info, st, fused_variant(d));
+      } else {
+        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);
+        if (e == hipSuccess) e = stap::launch_solve(d, cov, pd.steer, pd.w, pd.info, st);
+      }
+      if (e == hipSuccess) e = stap::launch_inner(d, pd.w, pd.snap, pd.power, nullptr, st);
+      if (e != hipSuccess) return STAP_ERR_HIP;
+    }
+    return STAP_OK;
+  }
+
+  // Batched: order by per-system cost, number the systems, upload the table.
+  std::stable_sort(desc.begin(), desc.end(), [](const stap::ProbDesc& a, const stap::ProbDesc& b) {
+    return system_cost(a.d) > system_cost(b.d);
+  });
+  long long total = 0;
+  int max_dof = 0, max_steer = 0;
+  for (auto& pd : desc) {
+    pd.sys_begin = total;
+    total += (long long)pd.d.P * pd.d.B;
+    max_dof = std::max(max_dof, pd.d.D);
+    max_steer = std::max(max_steer, pd.d.S);
+  }
+  Dims cls = desc[0].d;
+  cls.D = max_dof;
+  cls.S = max_steer;
+  const int ty = fused_variant(cls);
+  const int prec = probs[0].precision, refine = probs[0].refine_steps;
+
+  if (hipMemcpyAsync(table, desc.data(), desc.size() * sizeof(stap::ProbDesc), hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return STAP_ERR_HIP;
+
+  // Doppler launches, one per pulse count (at most kMaxBatchArg cubes each).
+  std::vector<std::pair<stap::BatchIndex, int>> dop;
+  for (int P : {32, 64, 128, 256, 512}) {
+    stap::BatchIndex bi;
+    bi.n = 0;
+    int tiles = 0;
+    for (int i = 0; i < n_probs; ++i) {
+      if (desc[i].d.P != P) continue;
+      if (bi.n == stap::kMaxBatchArg) {
+        bi.tile_begin[bi.n] = tiles;
+        dop.push_back({bi, P});
+        bi.n = 0;
+        tiles = 0;
+      }
+      bi.prob[bi.n] = i;
+      bi.tile_begin[bi.n] = tiles;
+      tiles += stap::doppler_tiles(desc[i].d);
+      ++bi.n;
+    }
+    if (bi.n > 0) {
+      bi.tile_begin[bi.n] = tiles;
+      dop.push_back({bi, P});
+    }
+  }
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    for (auto& x : dop) {
+      hipError_t e = stap::launch_doppler_batched(x.second, table, x.first, x.first.tile_begin[x.first.n], s);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = stap::launch_fused_batched(table, n_probs, total, max_dof, max_steer, prec, refine, ty, s);
+    if (e != hipSuccess) return e;
+    return stap::launch_inner_batched(table, n_probs, total, max_dof, max_steer, prec, s);
+  };
+
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return STAP_ERR_HIP;
+  if (!g_use_graphs || cap != hipStreamCaptureStatusNone) return hip_status(enqueue(st));
+
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return STAP_ERR_HIP;
+  std::string key = std::to_string(dev) + "|" + std::to_string((uintptr_t)workspace) + "|" +
+                    std::to_string(prec) + "|" + std::to_string(refine) + "|" + std::to_string(ty);
+  for (auto& pd : desc) {
+    key += "|" + std::to_string(pd.d.C) + "," + std::to_string(pd.d.P) + "," + std::to_string(pd.d.R) + "," +
+           std::to_string(pd.d.T) + "," + std::to_string(pd.d.B) + "," + std::to_string(pd.d.S);
+  }
+  GraphCache& gc = graphs();
+  std::lock_guard<std::mutex> lock(gc.mu);
+  auto it = gc.exec.find(key);
+  if (it == gc.exec.end()) {
+    hipStream_t cs;
+    auto sit = gc.capture_stream.find(dev);
+    if (sit == gc.capture_stream.end()) {
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return STAP_ERR_HIP;
+      gc.capture_stream[dev] = cs;
+    } else {
+      cs = sit->second;
+    }
+    hipGraph_t graph;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return STAP_ERR_HIP;
+    const hipError_t e = enqueue(cs);
+    const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) return STAP_ERR_HIP;
+    hipGraphExec_t ge;
+    const hipError_t e3 = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return STAP_ERR_HIP;
+    it = gc.exec.emplace(key, ge).first;
+  }
+  return hip_status(hipGraphLaunch(it->second, st));
 }
+
+void stap_use_graphs(int32_t enable) { g_use_graphs = enable != 0; }
 
 const char* stap_status_string(stap_status status) {
   switch (status) {
@@ -205,6 +388,21 @@ const char* stap_status_string(stap_status status) {
   return "unknown status";
 }
 
-const char* stap_version(void) { return "0.1.0"; }
+stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine,
+                          int32_t variant) {
+  const int dc = dof_class(dof), sc = steer_class(n_steer);
+  if (kind != 0 || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0) return STAP_ERR_ARG;
+  if (variant != 0 && variant != 16 && variant != 32) return STAP_ERR_ARG;
+  g_tune[kind][dc][sc][precision][refine > 0 ? 1 : 0] = (int8_t)variant;
+  return STAP_OK;
+}
+
+int32_t stap_tune_get(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine) {
+  const int dc = dof_class(dof), sc = steer_class(n_steer);
+  if (kind != 0 || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0) return -1;
+  return g_tune[kind][dc][sc][precision][refine > 0 ? 1 : 0];
+}
+
+const char* stap_version(void) { return "0.2.0"; }
 
 }  // extern "C"

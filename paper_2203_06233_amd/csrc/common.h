@@ -214,6 +214,10 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+__device__ __forceinline__ uint4 negbf8(uint4 u) {
+  return make_uint4(u.x ^ 0x80008000u, u.y ^ 0x80008000u, u.z ^ 0x80008000u, u.w ^ 0x80008000u);
+}
+
 // Split x into three bf16 terms with x = h + m + l to about 24 bits: each
 // residual is exact in FP32, so h*h' etc. are exact products in FP32.
 __device__ __forceinline__ void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {

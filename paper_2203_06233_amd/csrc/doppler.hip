@@ -28,9 +28,10 @@ struct FftShape {
   static constexpr int RT = 256 / P2;  // range cells per workgroup
 };
 
+// One workgroup's tile: channel c, range cells r0 .. r0+RT-1 of one cube.
 template <int P>
-__global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__ cube,
-                                                      float2* __restrict__ snap, Dims d) {
+__device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, float2* __restrict__ snap,
+                                             const Dims& d, int c, int r0) {
   using Sh = FftShape<P>;
   constexpr int P1 = Sh::P1, P2 = Sh::P2, RT = Sh::RT;
   __shared__ float2 ybuf[P1 * P2 * RT];  // [k1][n2][cell]
@@ -38,8 +39,6 @@ __global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__
   __shared__ float hwin[P];
 
   const int tid = threadIdx.x;
-  const int c = blockIdx.y;
-  const int r0 = blockIdx.x * RT;
 
   for (int m = tid; m < P; m += 256) {
     tw[m] = make_float2(kTwTab<P>.c[m], -kTwTab<P>.s[m]);
@@ -87,6 +86,52 @@ __global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__
     }
     __syncthreads();
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__ cube,
+                                                      float2* __restrict__ snap, Dims d) {
+  doppler_tile<P>(cube, snap, d, blockIdx.y, blockIdx.x * FftShape<P>::RT);
+}
+
+// Batched: the workgroups of several cubes with the same P in one grid.
+template <int P>
+__global__ __launch_bounds__(256) void doppler_batched_kernel(const ProbDesc* __restrict__ desc, BatchIndex bi) {
+  constexpr int RT = FftShape<P>::RT;
+  const int g = blockIdx.x;
+  int j = 0;
+  while (j + 1 < bi.n && bi.tile_begin[j + 1] <= g) ++j;
+  const ProbDesc& pd = desc[bi.prob[j]];
+  const Dims d = pd.d;
+  const int local = g - bi.tile_begin[j];
+  const int ntr = (d.R + RT - 1) / RT;
+  doppler_tile<P>(pd.cube, pd.snap, d, local / ntr, (local % ntr) * RT);
+}
+
+int doppler_tiles(const Dims& d) {
+  int rt = 0;
+  switch (d.P) {
+    case 32: rt = FftShape<32>::RT; break;
+    case 64: rt = FftShape<64>::RT; break;
+    case 128: rt = FftShape<128>::RT; break;
+    case 256: rt = FftShape<256>::RT; break;
+    case 512: rt = FftShape<512>::RT; break;
+    default: return 0;
+  }
+  return ((d.R + rt - 1) / rt) * d.C;
+}
+
+hipError_t launch_doppler_batched(int P, const ProbDesc* desc, const BatchIndex& bi, int tiles, hipStream_t st) {
+  if (tiles <= 0) return hipSuccess;
+  switch (P) {
+    case 32: hipLaunchKernelGGL(doppler_batched_kernel<32>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 64: hipLaunchKernelGGL(doppler_batched_kernel<64>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 128: hipLaunchKernelGGL(doppler_batched_kernel<128>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 256: hipLaunchKernelGGL(doppler_batched_kernel<256>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 512: hipLaunchKernelGGL(doppler_batched_kernel<512>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipStream_t st) {

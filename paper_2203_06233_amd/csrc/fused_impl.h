@@ -1,0 +1,109 @@
+// Fused covariance -> Cholesky -> solve per system (the path of stap_run):
+// the loaded covariance of a (Doppler bin, training block) never leaves the
+// compute unit.
+//   phase 1  cov_accumulate() (cov_impl.h) on MFMA; the FP64 trace gives
+//            delta; the tiles are written into LDS as the packed lower
+//            triangle of R_L, reusing the snapshot staging buffer;
+//   phase 2  solve_system() (solve_impl.h) reads R_L from that packed copy,
+//            which also feeds the FP64 refinement residual.
+// Compared with the stage kernels this saves the covariance round trip
+// through HBM (P*B*D*D*8 bytes written and half of it read back).
+#pragma once
+
+#include "common.h"
+#include "cov_impl.h"
+#include "kernels.h"
+#include "solve_impl.h"
+
+namespace stap {
+
+
+struct PackedR {
+  const float2* Rp;
+  __device__ float2 lower(int i, int k) const { return Rp[i * (i + 1) / 2 + k]; }
+};
+
+// System `sys` of one cube: wout and info_out are the cube's arrays.
+template <int TY, int NA, int NB, int NVS, int MODE, bool REFINE>
+__device__ __forceinline__ void fused_system(const float2* __restrict__ snap, const float2* __restrict__ steer,
+                                             float2* __restrict__ wout, int* __restrict__ info_out,
+                                             const Dims& d, int sys) {
+  using K = SolveCfg<TY, NA, NB, NVS>;
+  using C = CovCfg<K::DPC, K::NT / 64, MODE>;
+  constexpr int PACK = K::kPacked * 8;
+  constexpr int UB = REFINE ? K::SPR * K::DPC * 8 : 0;
+  constexpr int BYTES = C::LDS_BYTES > PACK + UB ? C::LDS_BYTES : PACK + UB;
+  __shared__ __align__(16) unsigned char lds[BYTES];
+  __shared__ SolveShared<K> sh;
+  __shared__ double dsum[K::DPC];
+  __shared__ float red[K::NT / 64];
+  __shared__ float s_delta;
+
+  const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
+  const int D = d.D;
+  const float2* X = snap + (long long)k * D * d.R + (long long)b * d.N;
+  floatx4 accR[C::TPW], accI[C::TPW];
+  cov_accumulate<C>(X, d.R, D, d.N, lds, red, accR, accI);
+  const float dl = cov_delta<C>(accR, D, d.eps, dsum, &s_delta);
+  __syncthreads();  // the staging buffer is dead: reuse it for R_L
+  float2* Rp = reinterpret_cast<float2*>(lds);
+  cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
+  __syncthreads();
+  float2* ub = reinterpret_cast<float2*>(lds + PACK);
+  solve_system<K, REFINE>(PackedR{Rp}, Rp, ub, steer, wout + (long long)sys * d.S * D,
+                          info_out ? info_out + sys : nullptr, d, sh);
+}
+
+
+template <int TY, int NA, int NB, int NVS, int MODE, bool REFINE>
+__global__ __launch_bounds__(16 * TY) void fused_kernel(const float2* __restrict__ snap,
+                                                        const float2* __restrict__ steer,
+                                                        float2* __restrict__ wout, int* __restrict__ info_out,
+                                                        Dims d) {
+  fused_system<TY, NA, NB, NVS, MODE, REFINE>(snap, steer, wout, info_out, d, blockIdx.x);
+}
+
+// Persistent: a grid-stride loop over the systems of every cube of the
+// table.  Cubes are ordered by cost (largest first), so the most expensive
+// systems are handed out first.
+template <int TY, int NA, int NB, int NVS, int MODE, bool REFINE>
+__global__ __launch_bounds__(16 * TY) void fused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
+                                                                long long total) {
+  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].sys_begin <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProbDesc& pd = desc[lo];
+    const Dims d = pd.d;
+    fused_system<TY, NA, NB, NVS, MODE, REFINE>(pd.snap, pd.steer, pd.w, pd.info, d, (int)(g - pd.sys_begin));
+    __syncthreads();
+  }
+}
+
+template <int TY, int NA, int NB, int NVS, int MODE>
+hipError_t go_fused_batched(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st) {
+  // enough workgroups to fill every CU a few times over, never more than systems
+  const long long want = 256LL * (TY == 16 ? 4 : 2);
+  const dim3 grid((unsigned)(total < want ? total : want)), block(16 * TY);
+  if (refine == 0)
+    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, false>), grid, block, 0, st, desc, n, total);
+  else
+    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, true>), grid, block, 0, st, desc, n, total);
+  return hipGetLastError();
+}
+
+template <int TY, int NA, int NB, int NVS, int MODE>
+hipError_t go_fused(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
+                    hipStream_t st) {
+  const dim3 grid(d.P * d.B), block(16 * TY);
+  if (d.refine == 0)
+    hipLaunchKernelGGL((fused_kernel<TY, NA, NB, NVS, MODE, false>), grid, block, 0, st, snap, steer, w, info, d);
+  else
+    hipLaunchKernelGGL((fused_kernel<TY, NA, NB, NVS, MODE, true>), grid, block, 0, st, snap, steer, w, info, d);
+  return hipGetLastError();
+}
+
+}  // namespace stap

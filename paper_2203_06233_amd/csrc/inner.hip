@@ -3,12 +3,17 @@
 //
 //   y[k][s][r] = w_{k,b(r),s}^H X[k][:, r],   power = |y|^2.
 //
-// One workgroup per system (k, b): a complex (S x D) x (D x N) product on
-// v_mfma_f32_16x16x4_f32,
+// One workgroup per system (k, b): a complex (S x D) x (D x N) product,
 //   Re y = Wr.Xr + Wi.Xi,   Im y = Wr.Xi - Wi.Xr.
 // The weights of the system are staged once in LDS; each wave owns a set of
 // 16-cell range tiles and all steering tiles, so every snapshot element is
 // read from HBM exactly once, coalesced along range.
+//   FP32   v_mfma_f32_16x16x4_f32 on the FP32 operands.
+//   BF16   (mixed path) weights and snapshots are split exactly into three
+//          BF16 terms each; the six products hh, hm, mh, hl, lh, mm run on
+//          v_mfma_f32_16x16x32_bf16, the hh term in its own accumulator, so
+//          the output keeps FP32-level error (the filter output cancels the
+//          clutter, so a single BF16 term would not).
 #include "common.h"
 #include "kernels.h"
 
@@ -17,15 +22,13 @@ namespace stap {
 namespace {
 
 template <int ST, int DP>
-__global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ wts,
-                                                    const float2* __restrict__ snap,
-                                                    float* __restrict__ power, float2* __restrict__ yout,
-                                                    Dims d) {
+__device__ __forceinline__ void inner_system(const float2* __restrict__ wts, const float2* __restrict__ snap,
+                                             float* __restrict__ power, float2* __restrict__ yout,
+                                             const Dims& d, int sys) {
   constexpr int SP = ST * 16;
   constexpr int WPITCH = DP + 1;
   __shared__ float2 ws[SP * WPITCH];  // [s][d]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int sys = blockIdx.x;
   const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
   const int D = d.D, S = d.S, N = d.N;
   const float2* W = wts + (long long)sys * S * D;
@@ -36,33 +39,181 @@ __global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ w
   __syncthreads();
   const float2* X = snap + (long long)k * D * d.R + (long long)b * N;
   const int ntile = (N + 15) / 16;
-  for (int rt = wave; rt < ntile; rt += 4) {
-    const int r = rt * 16 + (lane & 15);
-    const bool live = r < N;
-    floatx4 accR[ST], accI[ST];
+  // each wave takes RTW range tiles at a time; the snapshot loads of the
+  // next 16-row chunk are issued before the MFMAs of the current one
+  constexpr int RTW = 2;
+  for (int rt0 = wave * RTW; rt0 < ntile; rt0 += 4 * RTW) {
+    int r[RTW];
+    bool live[RTW];
 #pragma unroll
-    for (int t = 0; t < ST; ++t) {
-      accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-      accI[t] = accR[t];
+    for (int w = 0; w < RTW; ++w) {
+      r[w] = (rt0 + w) * 16 + (lane & 15);
+      live[w] = (rt0 + w < ntile) && r[w] < N;
     }
-#pragma unroll 1
-    for (int q0 = 0; q0 < DP; q0 += 16) {
-      float2 xv[4];
+    floatx4 accR[RTW][ST], accI[RTW][ST];
+#pragma unroll
+    for (int w = 0; w < RTW; ++w)
+#pragma unroll
+      for (int t = 0; t < ST; ++t) {
+        accR[w][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        accI[w][t] = accR[w][t];
+      }
+    auto load = [&](int q0, float2 (&xv)[RTW][4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = q0 + 4 * u + (lane >> 4);
-        xv[u] = (live && q < D) ? X[(long long)q * d.R + r] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int w = 0; w < RTW; ++w)
+          xv[w][u] = (live[w] && q < D) ? X[(long long)q * d.R + r[w]] : make_float2(0.f, 0.f);
       }
+    };
+    float2 cur[RTW][4], nxt[RTW][4];
+    load(0, cur);
+#pragma unroll 1
+    for (int q0 = 0; q0 < DP; q0 += 16) {
+      if (q0 + 16 < DP) load(q0 + 16, nxt);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = q0 + 4 * u + (lane >> 4);
 #pragma unroll
         for (int t = 0; t < ST; ++t) {
           const float2 wv = ws[(t * 16 + (lane & 15)) * WPITCH + q];
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, xv[u].x, accR[t], 0, 0, 0);
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, xv[u].y, accR[t], 0, 0, 0);
-          accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, xv[u].y, accI[t], 0, 0, 0);
-          accI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wv.y, xv[u].x, accI[t], 0, 0, 0);
+#pragma unroll
+          for (int w = 0; w < RTW; ++w) {
+            accR[w][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, cur[w][u].x, accR[w][t], 0, 0, 0);
+            accR[w][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, cur[w][u].y, accR[w][t], 0, 0, 0);
+            accI[w][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, cur[w][u].y, accI[w][t], 0, 0, 0);
+            accI[w][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-wv.y, cur[w][u].x, accI[w][t], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int w = 0; w < RTW; ++w)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[w][u] = nxt[w][u];
+    }
+#pragma unroll
+    for (int w = 0; w < RTW; ++w) {
+      if (!live[w]) continue;
+      const long long rr = (long long)b * N + r[w];
+#pragma unroll
+      for (int t = 0; t < ST; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int s = t * 16 + 4 * (lane >> 4) + i;
+          if (s < S) {
+            const float re = accR[w][t][i], im = accI[w][t][i];
+            const long long o = ((long long)k * S + s) * d.R + rr;
+            power[o] = re * re + im * im;
+            if (yout) yout[o] = make_float2(re, im);
+          }
+        }
+    }
+  }
+}
+
+__device__ __forceinline__ floatx4 mfma_bf16x(uint4 a, uint4 b, floatx4 c) {
+  typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b),
+                                                 c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned int pack2(unsigned short lo, unsigned short hi) {
+  return (unsigned int)lo | ((unsigned int)hi << 16);
+}
+
+// Split-BF16 variant.  LDS holds the weights as six planes
+// [re h, re m, re l, im h, im m, im l][s][d] (d padded to DP, pitch DP + 8).
+template <int ST, int DP>
+__device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts, const float2* __restrict__ snap,
+                                                  float* __restrict__ power, float2* __restrict__ yout,
+                                                  const Dims& d, int sys) {
+  constexpr int SP = ST * 16;
+  constexpr int PITCH = DP + 8;              // bf16 units per row
+  constexpr int PS = SP * PITCH / 2;         // plane stride in uint32
+  __shared__ __align__(16) unsigned int wp[6 * PS];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
+  const int D = d.D, S = d.S, N = d.N;
+  const float2* W = wts + (long long)sys * S * D;
+  for (int e = tid; e < SP * (DP / 2); e += 256) {
+    const int s = e / (DP / 2), q = 2 * (e % (DP / 2));
+    float2 w0 = make_float2(0.f, 0.f), w1 = w0;
+    if (s < S) {
+      if (q < D) w0 = W[s * D + q];
+      if (q + 1 < D) w1 = W[s * D + q + 1];
+    }
+    unsigned short h0, m0, l0, h1, m1, l1;
+    const int o = s * (PITCH / 2) + q / 2;
+    split3(w0.x, h0, m0, l0);
+    split3(w1.x, h1, m1, l1);
+    wp[0 * PS + o] = pack2(h0, h1);
+    wp[1 * PS + o] = pack2(m0, m1);
+    wp[2 * PS + o] = pack2(l0, l1);
+    split3(w0.y, h0, m0, l0);
+    split3(w1.y, h1, m1, l1);
+    wp[3 * PS + o] = pack2(h0, h1);
+    wp[4 * PS + o] = pack2(m0, m1);
+    wp[5 * PS + o] = pack2(l0, l1);
+  }
+  __syncthreads();
+  const uint4* wp4 = reinterpret_cast<const uint4*>(wp);
+  const float2* X = snap + (long long)k * D * d.R + (long long)b * N;
+  const int ntile = (N + 15) / 16;
+  constexpr int PA[5] = {0, 1, 0, 2, 1};
+  constexpr int PB[5] = {1, 0, 2, 0, 1};
+  for (int rt = wave; rt < ntile; rt += 4) {
+    const int r = rt * 16 + (lane & 15);
+    const bool live = r < N;
+    floatx4 accR[ST], accI[ST], corR[ST], corI[ST];
+#pragma unroll
+    for (int t = 0; t < ST; ++t) {
+      accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      accI[t] = accR[t];
+      corR[t] = accR[t];
+      corI[t] = accR[t];
+    }
+#pragma unroll 1
+    for (int q0 = 0; q0 < DP; q0 += 32) {
+      // B operand: X[q0 + 8*(lane/16) + j][r], j = 0..7, split into 3 terms
+      unsigned int xb[6][4];
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const int q = q0 + 8 * (lane >> 4) + j;
+        const float2 x0 = (live && q < D) ? X[(long long)q * d.R + r] : make_float2(0.f, 0.f);
+        const float2 x1 = (live && q + 1 < D) ? X[(long long)(q + 1) * d.R + r] : make_float2(0.f, 0.f);
+        unsigned short h0, m0, l0, h1, m1, l1;
+        split3(x0.x, h0, m0, l0);
+        split3(x1.x, h1, m1, l1);
+        xb[0][j / 2] = pack2(h0, h1);
+        xb[1][j / 2] = pack2(m0, m1);
+        xb[2][j / 2] = pack2(l0, l1);
+        split3(x0.y, h0, m0, l0);
+        split3(x1.y, h1, m1, l1);
+        xb[3][j / 2] = pack2(h0, h1);
+        xb[4][j / 2] = pack2(m0, m1);
+        xb[5][j / 2] = pack2(l0, l1);
+      }
+      uint4 Bv[6];
+#pragma unroll
+      for (int p = 0; p < 6; ++p) Bv[p] = make_uint4(xb[p][0], xb[p][1], xb[p][2], xb[p][3]);
+#pragma unroll
+      for (int t = 0; t < ST; ++t) {
+        const int o = (t * 16 + (lane & 15)) * (PITCH / 8) + q0 / 8 + (lane >> 4);
+        uint4 A[6];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) A[p] = wp4[p * (PS / 4) + o];
+        // Re += Wr Xr + Wi Xi ;  Im += Wr Xi - Wi Xr
+        accR[t] = mfma_bf16x(A[0], Bv[0], accR[t]);
+        accR[t] = mfma_bf16x(A[3], Bv[3], accR[t]);
+        accI[t] = mfma_bf16x(A[0], Bv[3], accI[t]);
+        accI[t] = mfma_bf16x(negbf8(A[3]), Bv[0], accI[t]);
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+          corR[t] = mfma_bf16x(A[PA[u]], Bv[PB[u]], corR[t]);
+          corR[t] = mfma_bf16x(A[3 + PA[u]], Bv[3 + PB[u]], corR[t]);
+          corI[t] = mfma_bf16x(A[PA[u]], Bv[3 + PB[u]], corI[t]);
+          corI[t] = mfma_bf16x(negbf8(A[3 + PA[u]]), Bv[PB[u]], corI[t]);
         }
       }
     }
@@ -74,7 +225,7 @@ __global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ w
         for (int i = 0; i < 4; ++i) {
           const int s = t * 16 + 4 * (lane >> 4) + i;
           if (s < S) {
-            const float re = accR[t][i], im = accI[t][i];
+            const float re = accR[t][i] + corR[t][i], im = accI[t][i] + corI[t][i];
             const long long o = ((long long)k * S + s) * d.R + rr;
             power[o] = re * re + im * im;
             if (yout) yout[o] = make_float2(re, im);
@@ -82,6 +233,57 @@ __global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ w
         }
     }
   }
+}
+
+template <int ST, int DP>
+__global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ wts, const float2* __restrict__ snap,
+                                                    float* __restrict__ power, float2* __restrict__ yout, Dims d) {
+  inner_system<ST, DP>(wts, snap, power, yout, d, blockIdx.x);
+}
+
+template <int ST, int DP>
+__global__ __launch_bounds__(256) void inner_bf16_kernel(const float2* __restrict__ wts,
+                                                         const float2* __restrict__ snap,
+                                                         float* __restrict__ power, float2* __restrict__ yout,
+                                                         Dims d) {
+  inner_bf16_system<ST, DP>(wts, snap, power, yout, d, blockIdx.x);
+}
+
+// Batched: one workgroup per system of every cube of the table.
+template <int ST, int DP, bool BF>
+__global__ __launch_bounds__(256) void inner_batched_kernel(const ProbDesc* __restrict__ desc, int n) {
+  const long long g = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].sys_begin <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const ProbDesc& pd = desc[lo];
+  const Dims d = pd.d;
+  if (BF) inner_bf16_system<ST, DP>(pd.w, pd.snap, pd.power, nullptr, d, (int)(g - pd.sys_begin));
+  else inner_system<ST, DP>(pd.w, pd.snap, pd.power, nullptr, d, (int)(g - pd.sys_begin));
+}
+
+template <int ST, bool BF>
+hipError_t go_inner_batched(const ProbDesc* desc, int n, long long total, int max_dof, hipStream_t st) {
+  const dim3 grid((unsigned)total), block(256);
+  if (max_dof <= 32) hipLaunchKernelGGL((inner_batched_kernel<ST, 32, BF>), grid, block, 0, st, desc, n);
+  else if (max_dof <= 64) hipLaunchKernelGGL((inner_batched_kernel<ST, 64, BF>), grid, block, 0, st, desc, n);
+  else if (max_dof <= 96) hipLaunchKernelGGL((inner_batched_kernel<ST, 96, BF>), grid, block, 0, st, desc, n);
+  else hipLaunchKernelGGL((inner_batched_kernel<ST, 128, BF>), grid, block, 0, st, desc, n);
+  return hipGetLastError();
+}
+
+template <int ST>
+hipError_t go_inner_bf16(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
+                         hipStream_t st) {
+  dim3 grid(d.P * d.B), block(256);
+  if (d.D <= 32) hipLaunchKernelGGL((inner_bf16_kernel<ST, 32>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 64) hipLaunchKernelGGL((inner_bf16_kernel<ST, 64>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 96) hipLaunchKernelGGL((inner_bf16_kernel<ST, 96>), grid, block, 0, st, w, snap, power, y, d);
+  else hipLaunchKernelGGL((inner_bf16_kernel<ST, 128>), grid, block, 0, st, w, snap, power, y, d);
+  return hipGetLastError();
 }
 
 template <int ST>
@@ -100,8 +302,34 @@ hipError_t go_inner_dp(const Dims& d, const float2* w, const float2* snap, float
 
 }  // namespace
 
+hipError_t launch_inner_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,
+                                int prec, hipStream_t st) {
+  if (max_dof > 128 || total_sys <= 0) return hipErrorInvalidValue;
+  const bool bf = prec != STAP_PREC_FP32;
+  switch ((max_steer + 15) / 16) {
+    case 1: return bf ? go_inner_batched<1, true>(desc, n, total_sys, max_dof, st)
+                      : go_inner_batched<1, false>(desc, n, total_sys, max_dof, st);
+    case 2: return bf ? go_inner_batched<2, true>(desc, n, total_sys, max_dof, st)
+                      : go_inner_batched<2, false>(desc, n, total_sys, max_dof, st);
+    case 3: return bf ? go_inner_batched<3, true>(desc, n, total_sys, max_dof, st)
+                      : go_inner_batched<3, false>(desc, n, total_sys, max_dof, st);
+    case 4: return bf ? go_inner_batched<4, true>(desc, n, total_sys, max_dof, st)
+                      : go_inner_batched<4, false>(desc, n, total_sys, max_dof, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_inner(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
                         hipStream_t st) {
+  if (d.prec != STAP_PREC_FP32 && d.D <= 128) {
+    switch ((d.S + 15) / 16) {
+      case 1: return go_inner_bf16<1>(d, w, snap, power, y, st);
+      case 2: return go_inner_bf16<2>(d, w, snap, power, y, st);
+      case 3: return go_inner_bf16<3>(d, w, snap, power, y, st);
+      case 4: return go_inner_bf16<4>(d, w, snap, power, y, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch ((d.S + 15) / 16) {
     case 1: return go_inner_dp<1>(d, w, snap, power, y, st);
     case 2: return go_inner_dp<2>(d, w, snap, power, y, st);

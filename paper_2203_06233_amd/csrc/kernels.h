@@ -6,6 +6,41 @@
 
 namespace stap {
 
+// One cube of a batched stap_run, as the kernels read it from the device
+// table in the workspace.
+struct ProbDesc {
+  Dims d;
+  const float2* cube;
+  const float2* steer;
+  float* power;
+  float2* w;
+  int* info;
+  float2* snap;
+  long long sys_begin;  // first global system index (problems ordered by cost)
+};
+
+// Kernel argument of a batched Doppler launch: up to kMaxBatchArg cubes with
+// the same P, their indices in the table and their first workgroup.
+constexpr int kMaxBatchArg = 64;
+struct BatchIndex {
+  int n;
+  int prob[kMaxBatchArg];
+  int tile_begin[kMaxBatchArg + 1];
+};
+
+// Workgroups of the Doppler kernel for one cube; batched Doppler launch.
+int doppler_tiles(const Dims& d);
+hipError_t launch_doppler_batched(int P, const ProbDesc* desc, const BatchIndex& bi, int tiles, hipStream_t st);
+
+// Persistent fused covariance -> solve over every system of every cube of the
+// table (all fused_supported, one precision); `cls` is the largest D and S.
+hipError_t launch_fused_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,
+                                int prec, int refine, int ty, hipStream_t st);
+
+// Inner products over every system of every cube of the table.
+hipError_t launch_inner_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,
+                                int prec, hipStream_t st);
+
 // X[P][D][R] <- windowed, time-staggered Doppler DFT of cube[C][P][R].
 hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipStream_t st);
 
@@ -16,6 +51,16 @@ hipError_t launch_covariance(const Dims& d, const float2* snap, float2* cov, flo
 // W[P][B][S][D] and info[P][B] from loaded covariances and steering V[S][D].
 hipError_t launch_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                         hipStream_t st);
+
+// Fused covariance -> solve (D <= 128, FP32 or BF16): W and info from X.
+// `ty` selects the thread grid (16 x 16 or 32 x 16; 32 needs D > 32).
+bool fused_supported(const Dims& d);
+hipError_t launch_fused(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
+                        hipStream_t st, int ty);
+hipError_t launch_fused16(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
+                          hipStream_t st);
+hipError_t launch_fused32(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
+                          hipStream_t st);
 
 // power[P][S][R] (and y if non-null) from W and X.
 hipError_t launch_inner(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,

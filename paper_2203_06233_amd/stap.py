@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import List, Optional, Sequence
 
 import torch
@@ -63,6 +64,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "stap_doppler": [P(Problem), vp, vp, vp],
         "stap_covariance": [P(Problem), vp, vp, vp, vp],
         "stap_solve_weights": [P(Problem), vp, vp, vp, vp, vp],
+        "stap_covariance_solve": [P(Problem), vp, vp, vp, vp, vp],
         "stap_inner_products": [P(Problem), vp, vp, vp, vp, vp],
         "stap_run": [P(Problem), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp), P(vp), vp, ctypes.c_size_t, vp],
         "stap_check_problem": [P(Problem)],
@@ -77,6 +79,13 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.stap_status_string.restype = ctypes.c_char_p
     lib.stap_version.argtypes = []
     lib.stap_version.restype = ctypes.c_char_p
+    i32 = ctypes.c_int32
+    lib.stap_tune_set.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.stap_tune_set.restype = ctypes.c_int
+    lib.stap_tune_get.argtypes = [i32, i32, i32, i32, i32]
+    lib.stap_tune_get.restype = i32
+    lib.stap_use_graphs.argtypes = [i32]
+    lib.stap_use_graphs.restype = None
     return lib
 
 
@@ -89,6 +98,20 @@ def _string(code: int) -> str:
 
 def version() -> str:
     return _lib.stap_version().decode()
+
+
+def tune_set(dof: int, n_steer: int, precision: str, refine: int, variant: int, kind: int = 0) -> None:
+    """Select the kernel variant for a shape class (see stap_tune_set)."""
+    _check(_lib.stap_tune_set(kind, dof, n_steer, PREC[precision], refine, variant), "stap_tune_set")
+
+
+def use_graphs(enable: bool) -> None:
+    """Replay batched stap_run launch chains from cached hipGraphs (default on)."""
+    _lib.stap_use_graphs(1 if enable else 0)
+
+
+def tune_get(dof: int, n_steer: int, precision: str, refine: int, kind: int = 0) -> int:
+    return int(_lib.stap_tune_get(kind, dof, n_steer, PREC[precision], refine))
 
 
 def problem(n_chan: int, n_pulse: int, n_range: int, tdof: int, n_block: int, n_steer: int,
@@ -205,6 +228,22 @@ def solve_weights(prob: Problem, cov: torch.Tensor, steer: torch.Tensor, w: Opti
     return w, info
 
 
+def covariance_solve(prob: Problem, snap: torch.Tensor, steer: torch.Tensor, w: Optional[torch.Tensor] = None,
+                     info: Optional[torch.Tensor] = None, stream=None):
+    """Fused covariance -> solve: weights w[P][B][S][D] and info[P][B]."""
+    if w is None:
+        w = _empty((prob.n_pulse, prob.n_block, prob.n_steer, prob.dof), torch.complex64, snap)
+    if info is None:
+        info = _empty((prob.n_pulse, prob.n_block), torch.int32, snap)
+    n = _sizes(prob)
+    _check(_lib.stap_covariance_solve(ctypes.byref(prob), _ptr(snap, torch.complex64, "snap", n["snap"]),
+                                      _ptr(steer, torch.complex64, "steer", n["steer"]),
+                                      _ptr(w, torch.complex64, "w", n["w"]),
+                                      _ptr(info, torch.int32, "info", n["info"]), _stream(stream)),
+           "stap_covariance_solve")
+    return w, info
+
+
 def inner_products(prob: Problem, w: torch.Tensor, snap: torch.Tensor, power: Optional[torch.Tensor] = None,
                    y: Optional[torch.Tensor] = None, want_y: bool = False, stream=None):
     """Output power[P][S][R] float32 (and y complex64 if requested)."""
@@ -265,3 +304,17 @@ class Runner:
 
 def run(probs: Sequence[Problem], cubes, steers, **kw) -> List[torch.Tensor]:
     return Runner(probs, device=cubes[0].device).run(cubes, steers, **kw)
+
+
+def _apply_tuning() -> None:
+    """Load the autotuner's cache (tune.py) into the library's variant table."""
+    if os.environ.get("STAP_NO_TUNE"):
+        return
+    from . import tune
+    try:
+        tune.apply_cache(sys.modules[__name__])
+    except (OSError, ValueError, KeyError):
+        pass
+
+
+_apply_tuning()

@@ -1,0 +1,138 @@
+"""Autotuner for the kernel variants of stap_run.
+
+For each shape class it runs stap_run on a seeded cube of that shape under
+every candidate variant of the fused covariance->solve kernel (16 x 16 or
+32 x 16 thread grid per system), keeps the fastest by HIP-event time, and
+stores the choice in a JSON cache keyed by GPU architecture, DOF class,
+steering class, precision and refinement.  The binding applies the cache
+(``tune_cache.json`` beside this file, or ``$STAP_TUNE_CACHE``) at import.
+
+    python -m paper_2203_06233_amd.tune [--workload large] [--reps 10]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+CACHE = os.environ.get("STAP_TUNE_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
+CANDIDATES = (16, 32)
+
+
+def arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def key(arch_name, dof, n_steer, precision, refine):
+    return f"{arch_name}|fused|dof<={dof}|s<={n_steer}|{precision}|refine={int(refine > 0)}"
+
+
+def load_cache(path=CACHE):
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply_cache(stap, path=CACHE, arch_name=None):
+    """Write every cached choice for this architecture into the library."""
+    cache = load_cache(path)
+    if not cache:
+        return 0
+    n = 0
+    for k, v in cache.items():
+        parts = k.split("|")
+        if arch_name is not None and parts[0] != arch_name:
+            continue
+        dof = int(parts[2].split("<=")[1])
+        s = int(parts[3].split("<=")[1])
+        prec = parts[4]
+        refine = int(parts[5].split("=")[1])
+        stap.tune_set(dof, s, prec, refine, int(v["variant"]))
+        n += 1
+    return n
+
+
+def tune_workload(wl, precision, refine, reps=10, warmup=3):
+    import torch
+
+    import synth
+    from paper_2203_06233_amd import stap
+
+    dev = torch.device("cuda:0")
+    cube = torch.from_numpy(synth.make_cube(wl)).to(dev)
+    V = torch.from_numpy(synth.steering(wl)).to(dev)
+    prob = stap.problem(wl.n_chan, wl.n_pulse, wl.n_range, wl.tdof, wl.n_block, wl.n_steer,
+                        load_eps=wl.load_eps, precision=precision, refine_steps=refine)
+    runner = stap.Runner([prob], device=dev)
+    power = torch.empty((wl.n_pulse, wl.n_steer, wl.n_range), dtype=torch.float32, device=dev)
+    W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device=dev)
+    times = {}
+    ref = None
+    for v in CANDIDATES:
+        if v == 32 and wl.dof <= 32:
+            continue
+        stap.tune_set(wl.dof, wl.n_steer, precision, refine, v)
+        for _ in range(warmup):
+            runner.run([cube], [V], powers=[power], weights=[W])
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            runner.run([cube], [V], powers=[power], weights=[W])
+        e1.record(st)
+        torch.cuda.synchronize()
+        times[v] = e0.elapsed_time(e1) / reps
+        # every variant computes the same weights up to rounding order
+        w = W.cpu()
+        if ref is None:
+            ref = w
+        else:
+            rel = float((w - ref).abs().max() / ref.abs().max())
+            if rel > 1e-3:
+                raise RuntimeError(f"variant {v} disagrees with variant {CANDIDATES[0]}: {rel}")
+    best = min(times, key=times.get)
+    stap.tune_set(wl.dof, wl.n_steer, precision, refine, best)
+    return best, times
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="all", choices=["all", "small", "medium", "large", "uneven"])
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import synth
+
+    sel = {"small": [synth.SMALL], "medium": [synth.MEDIUM], "large": [synth.LARGE],
+           "uneven": synth.uneven_batch(8)}
+    wls = sum(sel.values(), []) if args.workload == "all" else sel[args.workload]
+    a = arch()
+    cache = load_cache(args.out)
+    dof_cls = (16, 32, 48, 64, 96, 128, 160, 192)
+    s_cls = (16, 32, 64)
+    seen = set()
+    for wl in wls:
+        dc = next(c for c in dof_cls if wl.dof <= c)
+        sc = next(c for c in s_cls if wl.n_steer <= c)
+        for precision, refine in (("fp32", 0), ("bf16", 1), ("bf16", 0)):
+            k = key(a, dc, sc, precision, refine)
+            if k in seen:
+                continue
+            seen.add(k)
+            best, times = tune_workload(wl, precision, refine, reps=args.reps)
+            cache[k] = {"variant": best, "ms": {str(v): t for v, t in times.items()}, "workload": wl.name}
+            print(json.dumps({"key": k, **cache[k]}), flush=True)
+    with open(args.out, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    print(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

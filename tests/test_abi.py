@@ -98,9 +98,9 @@ def test_entry_points_reject_before_touching_the_device(binding):
     assert lib.stap_inner_products(bp, fake, fake, None, None, None) == -1
     bad = binding.problem(**dict(GOOD, n_range=500))
     assert lib.stap_doppler(ctypes.byref(bad), fake, fake, None) == -2
-    # D > 128 is valid for the Doppler and covariance stages but not the solve
+    # null info is rejected for the solve
     big = binding.problem(n_chan=64, n_pulse=512, n_range=32768, tdof=3, n_block=256, n_steer=64)
-    assert lib.stap_solve_weights(ctypes.byref(big), fake, fake, fake, fake, None) == -6
+    assert lib.stap_solve_weights(ctypes.byref(big), fake, fake, fake, None, None) == -1
 
 
 def test_run_rejects_before_touching_the_device(binding):
@@ -121,12 +121,42 @@ def test_run_rejects_before_touching_the_device(binding):
     assert lib.stap_run(probs, 0, fake, fake, fake, None, None, ctypes.c_void_p(0x100000), need, None) == -1
 
 
+def test_tuning_table(binding):
+    lib = binding._lib
+    saved = binding.tune_get(96, 32, "bf16", 1)
+    try:
+        binding.tune_set(96, 32, "bf16", 1, 0)
+        assert binding.tune_get(96, 32, "bf16", 1) == 0
+        binding.tune_set(96, 32, "bf16", 1, 32)
+        assert binding.tune_get(96, 32, "bf16", 1) == 32
+        assert binding.tune_get(90, 20, "bf16", 2) == 32  # same class
+        binding.tune_set(96, 32, "bf16", 1, 16)
+        assert binding.tune_get(96, 32, "bf16", 1) == 16
+    finally:
+        binding.tune_set(96, 32, "bf16", 1, saved)
+    assert lib.stap_tune_set(0, 96, 32, 1, 1, 24) == -1
+    assert lib.stap_tune_set(1, 96, 32, 1, 1, 16) == -1
+    assert lib.stap_tune_set(0, 200, 32, 1, 1, 16) == -1
+    assert lib.stap_tune_get(0, 96, 65, 1, 1) == -1
+
+
 def test_workspace_size_formula(binding):
     p = binding.problem(**GOOD)
     P, D, R, B, S = 64, 12, 512, 32, 8
 
     def up(x):
         return (x + 255) // 256 * 256
-    want = up(P * D * R * 8) + up(P * B * D * D * 8) + up(P * B * 4) + up(P * B * S * D * 8) + up(P * B * 4)
-    assert binding.workspace_size([p]) == want
-    assert binding.workspace_size([p, p]) == 2 * want
+    table = 128  # one problem descriptor
+    per = up(P * D * R * 8) + up(P * B * S * D * 8) + up(P * B * 4)  # fused: no covariance
+    assert binding.workspace_size([p]) == up(table) + per
+    assert binding.workspace_size([p, p]) == up(2 * table) + 2 * per
+    # D > 128 keeps the covariance and delta in the workspace
+    q = binding.problem(n_chan=48, n_pulse=32, n_range=256, tdof=3, n_block=2, n_steer=20)
+    P, D, R, B, S = 32, 144, 256, 2, 20
+    per_q = (up(P * D * R * 8) + up(P * B * D * D * 8) + up(P * B * 4) + up(P * B * S * D * 8)
+             + up(P * B * 4))
+    assert binding.workspace_size([q]) == up(table) + per_q
+    # FP8 does not use the fused kernel either
+    p8 = binding.problem(**dict(GOOD, precision="fp8"))
+    P, D, R, B, S = 64, 12, 512, 32, 8
+    assert binding.workspace_size([p8]) == up(table) + per + up(P * B * D * D * 8) + up(P * B * 4)

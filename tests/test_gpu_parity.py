@@ -145,7 +145,8 @@ def _solve_case(wl):
 @pytest.mark.parametrize("refine", [0, 1, 2])
 @pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 1024, 3, 16, 16),
                                           (32, 32, 256, 3, 2, 32), (32, 32, 256, 3, 2, 64),
-                                          (40, 32, 256, 3, 2, 20)], ids=str)
+                                          (40, 32, 256, 3, 2, 20), (48, 32, 256, 3, 2, 20),
+                                          (64, 32, 256, 3, 2, 64), (60, 32, 512, 3, 2, 33)], ids=str)
 def test_solve_parity(stap, shape, refine):
     wl = tiny_wl(shape)
     RL32, V, Wo, Go, Io = _solve_case(wl)
@@ -227,15 +228,17 @@ def test_white_snapshots_give_steering_weights(stap):
 
 # ------------------------------------------------------------ inner products
 
-@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (32, 32, 256, 3, 2, 64)], ids=str)
-def test_inner_parity(stap, shape):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (32, 32, 256, 3, 2, 64),
+                                          (64, 32, 256, 3, 2, 64)], ids=str)
+def test_inner_parity(stap, shape, precision):
     wl = tiny_wl(shape)
     cube = synth.make_cube(wl)
     X32 = orc.doppler(cube, wl.tdof).astype(np.complex64)
     o = orc.run_from_snapshots(X32.astype(np.complex128), synth.steering(wl), wl.n_block, wl.load_eps)
     W32 = o["W"].astype(np.complex64)
     yo, po = orc.inner_products(W32.astype(np.complex128), X32.astype(np.complex128), wl.n_block)
-    power, y = stap.inner_products(prob_of(wl), dev(W32), dev(X32), want_y=True)
+    power, y = stap.inner_products(prob_of(wl, precision), dev(W32), dev(X32), want_y=True)
     power, y = host(power), host(y)
     P, D, R = X32.shape
     N = wl.n_cell
@@ -245,7 +248,7 @@ def test_inner_parity(stap, shape):
     dy = 4.0 * (D + 2) * U32 * l1
     assert np.all(np.abs(y - yo) <= dy)
     bp = 2 * np.abs(yo) * dy + dy ** 2 + 2 * U32 * po
-    _report("inner", shape=shape, max_ratio=float((np.abs(power - po) / bp).max()))
+    _report("inner", shape=shape, prec=precision, max_ratio=float((np.abs(power - po) / bp).max()))
     assert np.all(np.abs(power - po) <= bp)
 
 
@@ -331,12 +334,117 @@ def test_stages_equal_run_and_deterministic(stap):
     assert np.array_equal(p_stage, p1)
 
 
-def test_batched_run_equals_single(stap):
-    wls = synth.uneven_batch(4)
+@pytest.mark.parametrize("graphs", [True, False])
+@pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 1)])
+def test_batched_run_equals_single(stap, precision, refine, graphs):
+    """The batched path (one launch per kernel over every cube, persistent
+    covariance->solve kernel) gives each cube the single-cube result."""
+    wls = synth.uneven_batch(6)
+    cubes = [dev(synth.make_cube(w)) for w in wls]
+    Vs = [dev(synth.steering(w)) for w in wls]
+    probs = [prob_of(w, precision, refine) for w in wls]
+    stap.use_graphs(graphs)
+    try:
+        Ws = [torch.empty((w.n_pulse, w.n_block, w.n_steer, w.dof), dtype=torch.complex64, device="cuda")
+              for w in wls]
+        runner = stap.Runner(probs)
+        batched = [host(p) for p in runner.run(cubes, Vs, weights=Ws)]
+        Wb = [host(x) for x in Ws]
+        for i in range(len(wls)):
+            W1 = torch.empty_like(Ws[i])
+            single = host(stap.run([probs[i]], [cubes[i]], [Vs[i]], weights=[W1])[0])
+            assert metrics.rel_err(batched[i], single) <= 1e-6, i
+            assert metrics.rel_err(Wb[i], host(W1)) <= 1e-6, i
+    finally:
+        stap.use_graphs(True)
+
+
+def test_graph_replays_equal_eager(stap):
+    """Replays of the cached graph, with eager work and synchronisations
+    between them, all equal the eager result."""
+    wls = synth.uneven_batch(5)
     cubes = [dev(synth.make_cube(w)) for w in wls]
     Vs = [dev(synth.steering(w)) for w in wls]
     probs = [prob_of(w, "bf16", 1) for w in wls]
-    batched = [host(p) for p in stap.run(probs, cubes, Vs)]
-    for i in range(len(wls)):
-        single = host(stap.run([probs[i]], [cubes[i]], [Vs[i]])[0])
-        assert np.array_equal(batched[i], single)
+    runner = stap.Runner(probs)
+    stap.use_graphs(False)
+    eager = [host(p) for p in runner.run(cubes, Vs)]
+    stap.use_graphs(True)
+    try:
+        for rep in range(4):
+            got = [host(p) for p in runner.run(cubes, Vs)]
+            for a, b in zip(got, eager):
+                assert np.array_equal(a, b), rep
+            # unrelated eager work in between
+            x = torch.randn(1 << 20, device="cuda")
+            (x * 2).sum().item()
+    finally:
+        stap.use_graphs(True)
+
+
+def test_uneven_batch_64_sampled(stap):
+    """The 64-cube uneven batch in one stap_run; the oracle recomputes one
+    training block of every fourth cube."""
+    wls = synth.uneven_batch(64)
+    cubes_np = [synth.make_cube(w) for w in wls]
+    Vs_np = [synth.steering(w) for w in wls]
+    probs = [prob_of(w, "bf16", 1) for w in wls]
+    Ws = [torch.empty((w.n_pulse, w.n_block, w.n_steer, w.dof), dtype=torch.complex64, device="cuda") for w in wls]
+    infos = [torch.empty((w.n_pulse, w.n_block), dtype=torch.int32, device="cuda") for w in wls]
+    powers = stap.run(probs, [dev(c) for c in cubes_np], [dev(v) for v in Vs_np], weights=Ws, info=infos)
+    worst_w, worst_sl = 0.0, 0.0
+    for i in range(0, 64, 4):
+        w = wls[i]
+        assert np.all(host(infos[i]) == 0)
+        b = (7 * i) % w.n_block
+        N = w.n_cell
+        ob = orc.run_block(cubes_np[i][:, :, b * N:(b + 1) * N], Vs_np[i], w.tdof, w.load_eps)
+        Wb = host(Ws[i])[:, b]
+        worst_w = max(worst_w, metrics.rel_err(Wb, ob["W"][:, 0]))
+        worst_sl = max(worst_sl, float(metrics.sinr_loss_db(Wb, ob["W"][:, 0], Vs_np[i], ob["R_L"][:, 0]).max()))
+        assert metrics.rel_err(host(powers[i])[:, :, b * N:(b + 1) * N], ob["power"]) <= 1e-3
+    _report("uneven64", weights=worst_w, sinr_max=worst_sl)
+    assert worst_w <= 1e-3 and worst_sl <= 0.1
+
+
+@pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 0), ("bf16", 1)])
+def test_fused_variants_match_oracle(stap, precision, refine):
+    """Both thread grids of the fused covariance->solve kernel (selected
+    through the tuning table) against the oracle on the 48-DOF cube."""
+    wl = synth.MEDIUM
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+    out = {}
+    try:
+        for variant in (16, 32):
+            stap.tune_set(wl.dof, wl.n_steer, precision, refine, variant)
+            prob = prob_of(wl, precision, refine)
+            W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
+            power = stap.run([prob], [dev(cube)], [dev(V)], weights=[W])[0]
+            out[variant] = (host(power), host(W))
+    finally:
+        stap.tune_set(wl.dof, wl.n_steer, precision, refine, 0)
+    for variant, (power, W) in out.items():
+        we = metrics.rel_err(W, o["W"])
+        pe = metrics.rel_err(power, o["power"])
+        _report("fused", variant=variant, prec=precision, refine=refine, weights=we, power=pe)
+        assert we <= 1e-3
+        assert pe <= 1e-4
+    assert metrics.rel_err(out[32][1], out[16][1]) <= 1e-4
+
+
+def test_chain_dof_above_128(stap):
+    """D = 144 runs the stage covariance and the 32 x 16 solve inside stap_run."""
+    wl = tiny_wl((48, 32, 512, 3, 2, 20))
+    for precision, refine in (("fp32", 0), ("bf16", 1), ("fp8", 1)):
+        cube, V, power, W, info = _run_gpu(stap, wl, precision, refine)
+        o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+        assert np.all(info == 0)
+        we = metrics.rel_err(W, o["W"])
+        sl = metrics.sinr_loss_db(W, o["W"], V, o["R_L"])
+        _report("dof144", prec=precision, refine=refine, weights=we, sinr_max=float(sl.max()),
+                power=metrics.rel_err(power, o["power"]))
+        if precision != "fp8":
+            assert we <= 1e-3
+            assert sl.max() <= 0.1
