@@ -31,8 +31,7 @@ __device__ __forceinline__ void fused_system(const float2* __restrict__ snap, co
   using K = SolveCfg<TY, NA, NB, NVS>;
   using C = CovCfg<K::DPC, K::NT / 64, MODE>;
   constexpr int PACK = K::kPacked * 8;
-  constexpr int UB = REFINE ? K::SPR * K::DPC * 8 : 0;
-  constexpr int BYTES = C::LDS_BYTES > PACK + UB ? C::LDS_BYTES : PACK + UB;
+  constexpr int BYTES = C::LDS_BYTES > PACK ? C::LDS_BYTES : PACK;
   __shared__ __align__(16) unsigned char lds[BYTES];
   __shared__ SolveShared<K> sh;
   __shared__ double dsum[K::DPC];
@@ -49,9 +48,8 @@ __device__ __forceinline__ void fused_system(const float2* __restrict__ snap, co
   float2* Rp = reinterpret_cast<float2*>(lds);
   cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
   __syncthreads();
-  float2* ub = reinterpret_cast<float2*>(lds + PACK);
-  solve_system<K, REFINE>(PackedR{Rp}, Rp, ub, steer, wout + (long long)sys * d.S * D,
-                          info_out ? info_out + sys : nullptr, d, sh);
+  solve_system<K, REFINE, true>(PackedR{Rp}, Rp, steer, wout + (long long)sys * d.S * D,
+                                info_out ? info_out + sys : nullptr, d, sh);
 }
 
 

@@ -31,19 +31,15 @@ __global__ __launch_bounds__(16 * TY) void solve_kernel(const float2* __restrict
                                                         Dims d) {
   using K = SolveCfg<TY, NA, NB, NVS>;
   __shared__ SolveShared<K> sh;
-  extern __shared__ __align__(16) float2 dyn[];  // refinement: [packed R_L] then u
+  extern __shared__ __align__(16) float2 dyn[];  // refinement: packed R_L
   const int sys = blockIdx.x;
   GlobalR src{cov + (long long)sys * d.D * d.D, d.D};
-  float2* Rp = nullptr;
-  float2* ub = dyn;
   if (REFINE && K::kPackedInLds) {
-    Rp = dyn;
-    ub = dyn + K::kPacked;
     for (int i = threadIdx.x / 16; i < d.D; i += TY)
-      for (int k = threadIdx.x % 16; k <= i; k += 16) Rp[i * (i + 1) / 2 + k] = src.lower(i, k);
+      for (int k = threadIdx.x % 16; k <= i; k += 16) dyn[i * (i + 1) / 2 + k] = src.lower(i, k);
   }
-  solve_system<K, REFINE>(src, Rp, ub, steer, wout + (long long)sys * d.S * d.D,
-                          info_out ? info_out + sys : nullptr, d, sh);
+  solve_system<K, REFINE, K::kPackedInLds>(src, dyn, steer, wout + (long long)sys * d.S * d.D,
+                                           info_out ? info_out + sys : nullptr, d, sh);
 }
 
 template <int TY, int NA, int NB, int NVS>

@@ -36,15 +36,14 @@ struct SolveCfg {
   static constexpr bool kPackedInLds = DPC <= 128;
   static constexpr int kPacked = DPC * (DPC + 1) / 2;
   __host__ __device__ static constexpr bool slot(int a, int b) { return 16 * b <= TY * a + TY - 1; }
-  static size_t refine_lds_bytes() {
-    return ((kPackedInLds ? (size_t)kPacked : 0) + (size_t)SPR * DPC) * sizeof(float2);
-  }
+  static size_t refine_lds_bytes() { return (kPackedInLds ? (size_t)kPacked : 0) * sizeof(float2); }
 };
 
 template <class K>
 struct SolveShared {
-  float2 colL[2][K::DPX];
-  float2 colV[2][K::SPR];
+  float2 colL[2][K::DPX];  // column j below the pivot (zero at and above it)
+  float2 colV[2][K::SPR];  // column j of the steering rows
+  float colP[2];           // the pivot M[j][j]
   float invd[K::DPX];
   float gam[K::SPR];
 };
@@ -151,12 +150,11 @@ __device__ __forceinline__ void sweep_fwd(float2 (&x)[K::NVS][K::NB], const floa
 }
 
 // Solve one system.  src.lower(i, k) (k <= i) yields the loaded covariance;
-// Rp, if not null, is the same lower triangle packed row-major in LDS (row i
-// at i(i+1)/2) for the refinement residual; ub is LDS scratch of
-// K::SPR * K::DPC float2 (refinement only).  W is this system's [S][D]
-// output, info its status word (may be null).
-template <class K, bool REFINE, class RSrc>
-__device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, float2* ub,
+// with RP_LDS the refinement residual reads the same lower triangle packed
+// row-major from LDS at Rp (row i at i(i+1)/2), else through src.  W is this
+// system's [S][D] output, info its status word (may be null).
+template <class K, bool REFINE, bool RP_LDS, class RSrc>
+__device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp,
                                              const float2* __restrict__ steer, float2* __restrict__ W,
                                              int* __restrict__ info, const Dims& d, SolveShared<K>& sh) {
   constexpr int TY = K::TY, NA = K::NA, NB = K::NB, NVS = K::NVS, NT = K::NT, DPC = K::DPC;
@@ -181,55 +179,60 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
       vm[a][b] = (s < S && k < D) ? conjf2(steer[s * D + k]) : make_float2(0.f, 0.f);
     }
 
+  // Column j is published already masked: colL holds rows i > j (zero at
+  // and above the pivot), colP the pivot.  Every thread then forms
+  // li = c_i / piv for its rows and lk = c_k for its columns with no
+  // per-element test; finished rows and columns contribute zeros.
   int fail = 0;
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) {
     const int a0 = (16 * jb) / TY;
+    const int j0 = 16 * jb;
     if (tx == 0) {
 #pragma unroll
-      for (int a = a0; a < NA; ++a) sh.colL[0][ty + TY * a] = lm[a][jb];
+      for (int a = a0; a < NA; ++a) {
+        const int i = ty + TY * a;
+        sh.colL[0][i] = (i > j0) ? lm[a][jb] : make_float2(0.f, 0.f);
+        if (i == j0) sh.colP[0] = lm[a][jb].x;
+      }
 #pragma unroll
       for (int a = 0; a < NVS; ++a) sh.colV[0][ty + TY * a] = vm[a][jb];
     }
     __syncthreads();
     const int jend = min(16, D - 16 * jb);
     for (int jt = 0; jt < jend; ++jt) {
-      const int j = 16 * jb + jt;
+      const int j = j0 + jt;
       const int buf = jt & 1;
-      const float piv = sh.colL[buf][j].x;
+      const float piv = sh.colP[buf];
       if (!(piv > 0.f)) {
         fail = j + 1;
         break;
       }
-      const float dj = sqrtf(piv), rs = 1.f / dj;
+      const float dj = sqrtf(piv), rs = 1.f / dj, ip = rs * rs;
       float2 li[NA], lk[NB], lv[NVS];
 #pragma unroll
       for (int a = a0; a < NA; ++a) {
-        const int i = ty + TY * a;
-        const float2 c = sh.colL[buf][i];
-        li[a] = (i > j) ? make_float2(c.x * rs, c.y * rs) : make_float2(0.f, 0.f);
+        const float2 c = sh.colL[buf][ty + TY * a];
+        li[a] = make_float2(c.x * ip, c.y * ip);
       }
 #pragma unroll
-      for (int b = jb; b < NB; ++b) {
-        const int k = tx + 16 * b;
-        const float2 c = sh.colL[buf][k];
-        lk[b] = (k > j && k < D) ? make_float2(c.x * rs, c.y * rs) : make_float2(0.f, 0.f);
-      }
+      for (int b = jb; b < NB; ++b) lk[b] = sh.colL[buf][tx + 16 * b];
 #pragma unroll
       for (int a = 0; a < NVS; ++a) {
         const float2 c = sh.colV[buf][ty + TY * a];
-        lv[a] = make_float2(c.x * rs, c.y * rs);
+        lv[a] = make_float2(c.x * ip, c.y * ip);
       }
       if (tid == 0) sh.invd[j] = rs;
-      if (tx == jt) {  // finalise column j
+      if (tx == jt) {  // finalise column j from the owners' own raw values
 #pragma unroll
         for (int a = a0; a < NA; ++a) {
           const int i = ty + TY * a;
-          if (i > j) lm[a][jb] = li[a];
+          const float2 c = lm[a][jb];
+          if (i > j) lm[a][jb] = make_float2(c.x * rs, c.y * rs);
           else if (i == j) lm[a][jb] = make_float2(dj, 0.f);
         }
 #pragma unroll
-        for (int a = 0; a < NVS; ++a) vm[a][jb] = lv[a];
+        for (int a = 0; a < NVS; ++a) vm[a][jb] = make_float2(vm[a][jb].x * rs, vm[a][jb].y * rs);
       }
 #pragma unroll
       for (int a = a0; a < NA; ++a)
@@ -240,9 +243,13 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
       for (int a = 0; a < NVS; ++a)
 #pragma unroll
         for (int b = jb; b < NB; ++b) sub_mulc(vm[a][b], lv[a], lk[b]);
-      if (jt + 1 < jend && tx == jt + 1) {  // publish column j+1
+      if (jt + 1 < jend && tx == jt + 1) {  // publish column j+1, masked
 #pragma unroll
-        for (int a = a0; a < NA; ++a) sh.colL[buf ^ 1][ty + TY * a] = lm[a][jb];
+        for (int a = a0; a < NA; ++a) {
+          const int i = ty + TY * a;
+          sh.colL[buf ^ 1][i] = (i > j + 1) ? lm[a][jb] : make_float2(0.f, 0.f);
+          if (i == j + 1) sh.colP[buf ^ 1] = lm[a][jb].x;
+        }
 #pragma unroll
         for (int a = 0; a < NVS; ++a) sh.colV[buf ^ 1][ty + TY * a] = vm[a][jb];
       }
@@ -274,15 +281,11 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
 
   if (REFINE) {
     for (int it = 0; it < d.refine; ++it) {
-#pragma unroll
-      for (int a = 0; a < NVS; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) ub[(ty + TY * a) * DPC + tx + 16 * b] = vm[a][b];
-      __syncthreads();
       // conj(r_s[k]) = conj(v_s[k]) - sum_q conj(R[k][q]) conj(u_s[q]) in FP64.
-      // conj(R[k][q]) is the stored lower element (k, q) conjugated when
-      // q <= k, else the stored (q, k) as is; the choice is a select, not a
-      // branch.  With few accumulators all steering slots share one pass.
+      // conj(u_s[q]) for q = tx' + 16 b sits in register vm[a][b] of lane
+      // tx' of the same 16-lane group (same ty), so it is broadcast with a
+      // shuffle.  conj(R[k][q]) is the stored lower element (k, q) conjugated
+      // when q <= k, else the stored (q, k): a select, not a branch.
       float2 rv[NVS][NB];
       int kb[NB];
 #pragma unroll
@@ -295,7 +298,7 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
         const int kc = min(k, D - 1);
         const bool lower = q <= kc;
         float2 v;
-        if (K::kPackedInLds) {
+        if (RP_LDS) {
           v = Rp[lower ? kb[b] + q : q * (q + 1) / 2 + kc];
         } else {
           v = src.lower(lower ? kc : q, lower ? q : kc);
@@ -303,7 +306,31 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
         v.y = lower ? -v.y : v.y;
         return (k < D) ? v : make_float2(0.f, 0.f);
       };
-      auto finish = [&](int a, const double (&accr)[NB], const double (&acci)[NB]) {
+#pragma unroll
+      for (int a = 0; a < NVS; ++a) {
+        double accr[NB], acci[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          accr[b] = 0.0;
+          acci[b] = 0.0;
+        }
+#pragma unroll
+        for (int bq = 0; bq < NB; ++bq) {
+          const int qn = min(16, D - 16 * bq);
+          for (int t = 0; t < qn; ++t) {
+            const int q = 16 * bq + t;
+            const float ur_f = __shfl(vm[a][bq].x, t, 16);
+            const float ui_f = __shfl(vm[a][bq].y, t, 16);
+            const double ur = ur_f, ui = ui_f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const float2 v = fetch(q, b);
+              const double rr = v.x, ri = v.y;
+              accr[b] = fma(rr, ur, fma(-ri, ui, accr[b]));
+              acci[b] = fma(rr, ui, fma(ri, ur, acci[b]));
+            }
+          }
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int s = ty + TY * a, k = tx + 16 * b;
@@ -313,61 +340,6 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
           } else {
             rv[a][b] = make_float2(0.f, 0.f);
           }
-        }
-      };
-      constexpr bool kOnePass = NVS * NB <= 12;
-      if (kOnePass) {
-        double accr[NVS][NB], acci[NVS][NB];
-#pragma unroll
-        for (int a = 0; a < NVS; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            accr[a][b] = 0.0;
-            acci[a][b] = 0.0;
-          }
-        for (int q = 0; q < D; ++q) {
-          double rr[NB], ri[NB];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const float2 v = fetch(q, b);
-            rr[b] = v.x;
-            ri[b] = v.y;
-          }
-#pragma unroll
-          for (int a = 0; a < NVS; ++a) {
-            const float2 u = ub[(ty + TY * a) * DPC + q];
-            const double ur = u.x, ui = u.y;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              accr[a][b] = fma(rr[b], ur, fma(-ri[b], ui, accr[a][b]));
-              acci[a][b] = fma(rr[b], ui, fma(ri[b], ur, acci[a][b]));
-            }
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < NVS; ++a) finish(a, accr[a], acci[a]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < NVS; ++a) {
-          double accr[NB], acci[NB];
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            accr[b] = 0.0;
-            acci[b] = 0.0;
-          }
-          const float2* urow = ub + (ty + TY * a) * DPC;
-          for (int q = 0; q < D; ++q) {
-            const float2 u = urow[q];
-            const double ur = u.x, ui = u.y;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              const float2 v = fetch(q, b);
-              const double rr = v.x, ri = v.y;
-              accr[b] = fma(rr, ur, fma(-ri, ui, accr[b]));
-              acci[b] = fma(rr, ui, fma(ri, ur, acci[b]));
-            }
-          }
-          finish(a, accr, acci);
         }
       }
       sweep_fwd<K>(rv, lm, D, sh);
