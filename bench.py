@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="large", choices=["small", "medium", "large", "uneven"])
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--workload", default="large", choices=["small", "medium", "large", "xlarge", "uneven"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp8"],
+                    help="mixed-path precision (default: fp8 for xlarge, bf16 otherwise)")
     ap.add_argument("--refine", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -47,7 +48,7 @@ def parse():
     return ap.parse_args()
 
 
-WL = {"small": synth.SMALL, "medium": synth.MEDIUM, "large": synth.LARGE}
+WL = {"small": synth.SMALL, "medium": synth.MEDIUM, "large": synth.LARGE, "xlarge": synth.XLARGE}
 
 
 def kernel_work(wl, precision, refine):
@@ -101,11 +102,49 @@ def roofline_of(name, work, sec):
     return dict(bound=bound, achieved=ach / 1e12, peak=peak / 1e12, unit="TFLOP/s", frac=ach / peak)
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2203_06233_amd", "csrc")
+
+
+def kernel_source_hash():
+    """SHA-256 over the HIP sources of the library, in name order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, precision, refine):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary for this workload (FETCH_SIZE + WRITE_SIZE, each scaled by what
+    the counter reads for a copy of known size), or None when there is none
+    or the kernel sources changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_{precision}_r{refine}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_sha256") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes"])
+    except (KeyError, ValueError):
+        return None
+
 def main():
     args = parse()
+    if args.precision is None:
+        args.precision = "fp8" if args.workload == "xlarge" else "bf16"
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the path shards by range blocks with no collective, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the path would shard "
+              "by training blocks along range with no collective, which one GPU's share already shows",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -153,9 +192,14 @@ def main():
         return wall, ev_ms, powers, weights, info
 
     wall_m, ev_m, powers, weights, info = time_run(args.precision, args.refine)
-    out_power = [p.cpu().numpy() for p in powers]
-    out_w = [w.cpu().numpy() for w in weights]
-    out_info = [i.cpu().numpy() for i in info]
+    # keep on the host only what the accuracy check reads: three sampled
+    # training blocks of the first cube
+    w0 = wls[0]
+    N0 = w0.n_cell
+    acc_blocks = sorted({0, w0.n_block // 2, w0.n_block - 1})
+    out_w = {b: weights[0][:, b].cpu().numpy() for b in acc_blocks}
+    out_power = {b: powers[0][:, :, b * N0:(b + 1) * N0].cpu().numpy() for b in acc_blocks}
+    info_nonzero = int(sum(int((i != 0).sum().item()) for i in info))
     del powers, weights, info
     torch.cuda.empty_cache()
 
@@ -173,32 +217,42 @@ def main():
         w = wls[0]
         prob = mkprob(w, args.precision, args.refine)
         st = torch.cuda.current_stream()
-        # the kernels stap_run launches: Doppler, fused covariance->solve, inner
+        # the kernels stap_run launches: Doppler, fused covariance->solve (or,
+        # for D > 128 and FP8, covariance then solve), inner products
         snap = stap.doppler(prob, cubes[0])
-        wts, inf = stap.covariance_solve(prob, snap, steers[0])
+        calls = {"doppler": lambda: stap.doppler(prob, cubes[0], snap)}
+        try:
+            wts, inf = stap.covariance_solve(prob, snap, steers[0])
+            calls["covariance_solve"] = lambda: stap.covariance_solve(prob, snap, steers[0], wts, inf)
+            cov = None
+        except stap.StapError as e:
+            if e.code != -6:
+                raise
+            cov, dlt = stap.covariance(prob, snap)
+            wts, inf = stap.solve_weights(prob, cov, steers[0])
+            calls["covariance"] = lambda: stap.covariance(prob, snap, cov, dlt)
+            calls["solve"] = lambda: stap.solve_weights(prob, cov, steers[0], wts, inf)
         pwr = stap.inner_products(prob, wts, snap)
-        calls = {
-            "doppler": lambda: stap.doppler(prob, cubes[0], snap),
-            "covariance_solve": lambda: stap.covariance_solve(prob, snap, steers[0], wts, inf),
-            "inner": lambda: stap.inner_products(prob, wts, snap, pwr),
-        }
+        calls["inner"] = lambda: stap.inner_products(prob, wts, snap, pwr)
         work = kernel_work(w, args.precision, args.refine)
+        ksteps = max(1, min(args.steps, 20))
         for name, fn in calls.items():
             for _ in range(2):
                 fn()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
-            for _ in range(args.steps):
+            for _ in range(ksteps):
                 fn()
             e1.record(st)
             torch.cuda.synchronize()
-            sec = e0.elapsed_time(e1) / args.steps / 1e3
+            sec = e0.elapsed_time(e1) / ksteps / 1e3
             kern[name] = dict(ms=sec * 1e3, **roofline_of(name, work[name], sec))
         dom = max(kern, key=lambda k: kern[k]["ms"])
         r = kern[dom]
         roof = dict(kernel=dom, bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
-                    frac=r["frac"], traffic=None)
-        del snap, wts, inf, pwr
+                    frac=r["frac"], traffic=measured_traffic(dom, w.name, args.precision, args.refine))
+        del snap, wts, inf, pwr, cov
+        torch.cuda.empty_cache()
 
     # accuracy against the FP64 oracle on sampled training blocks
     from oracle import metrics
@@ -208,14 +262,14 @@ def main():
         w = wls[0]
         N = w.n_cell
         errs, sls, pes = [], [], []
-        for b in sorted({0, w.n_block // 2, w.n_block - 1}):
+        for b in acc_blocks:
             ob = orc.run_block(cubes_np[0][:, :, b * N:(b + 1) * N], steers_np[0], w.tdof, w.load_eps)
-            Wb = out_w[0][:, b]
+            Wb = out_w[b]
             errs.append(metrics.rel_err(Wb, ob["W"][:, 0]))
             sls.append(float(metrics.sinr_loss_db(Wb, ob["W"][:, 0], steers_np[0], ob["R_L"][:, 0]).max()))
-            pes.append(metrics.rel_err(out_power[0][:, :, b * N:(b + 1) * N], ob["power"]))
-        acc = dict(blocks=3, weights_rel_err=max(errs), sinr_loss_db_max=max(sls), power_rel_err=max(pes),
-                   info_nonzero=int(sum(int((i != 0).sum()) for i in out_info)))
+            pes.append(metrics.rel_err(out_power[b], ob["power"]))
+        acc = dict(blocks=len(acc_blocks), weights_rel_err=max(errs), sinr_loss_db_max=max(sls),
+                   power_rel_err=max(pes), info_nonzero=info_nonzero)
 
     cpu = None
     if not args.no_cpu and len(wls) == 1:

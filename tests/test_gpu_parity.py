@@ -83,7 +83,8 @@ def _cov_case(wl):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 512, 3, 8, 16)], ids=str)
+@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 512, 3, 8, 16),
+                                          (64, 32, 256, 3, 2, 64)], ids=str)
 def test_covariance_parity(stap, shape, precision):
     wl = tiny_wl(shape)
     X32, Rh, delta_o, RL = _cov_case(wl)
@@ -111,10 +112,11 @@ def test_covariance_exact_integers(stap, precision):
     covariance off the diagonal is bitwise the exact value (eps = 0)."""
     rng = np.random.default_rng(11)
     P = 32
-    for (D, N, B) in [(12, 16, 3), (48, 64, 2), (96, 128, 1), (17, 33, 2)]:
+    for (D, N, B) in [(12, 16, 3), (48, 64, 2), (96, 128, 1), (17, 33, 2), (192, 128, 1), (144, 40, 2)]:
         X = (rng.integers(-8, 9, (P, D, N * B)) + 1j * rng.integers(-8, 9, (P, D, N * B))).astype(np.complex64)
         X[:, 0, :] = 8  # every system's largest component is 8: FP8 scale 2^4
-        prob = binding().problem(D, P, N * B, 1, B, 1, load_eps=0.0, precision=precision)
+        C, T = (D, 1) if D <= 64 else (D // 3, 3)  # the covariance sees only D = T * C
+        prob = binding().problem(C, P, N * B, T, B, 1, load_eps=0.0, precision=precision)
         cov, delta = stap.covariance(prob, dev(X))
         cov, delta = host(cov), host(delta)
         want = orc.covariance(X.astype(np.complex128), B)
