@@ -174,13 +174,18 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs,
                      void* workspace, size_t workspace_bytes, void* stream);
 
 /* Kernel-variant selection, written by the autotuner (tune.py) and read by
- * stap_run.  kind 0 = the fused covariance->solve kernel.  An entry applies to
- * the shape class containing (dof, n_steer): dof classes end at
- * 16, 32, 48, 64, 96, 128, 160, 192 and steering classes at 16, 32, 64.
- * variant: 0 = built-in default, 16 or 32 = rows per register slot of the
- * solve (a 16 x 16 or 32 x 16 thread grid per system).  Not thread-safe with
- * respect to concurrent stap_run calls.  Returns STAP_ERR_ARG for values out
- * of range. */
+ * stap_run and stap_covariance_solve (kind 0, the fused covariance->solve
+ * kernel) and by stap_solve_weights and the stage path of stap_run (kind 1).
+ * An entry applies to the shape class containing (dof, n_steer): dof classes
+ * end at 16, 32, 48, 64, 96, 128, 160, 192 and steering classes at 16, 32, 64.
+ * variant: 0 = built-in default;
+ *          16 or 32 = column-sweep solve with 16 or 32 rows per register
+ *                     slot (a 16 x 16 or 32 x 16 thread grid per system);
+ *          4 or 8   = blocked solve on the FP32 matrix cores with 4 or 8
+ *                     waves per system (D <= 128 and refine_steps = 0; other
+ *                     requests in the class take the default).
+ * Not thread-safe with respect to concurrent stap_run calls.  Returns
+ * STAP_ERR_ARG for values out of range. */
 stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine,
                           int32_t variant);
 /* The variant stored for that class (0 = default), or -1 for invalid input. */

@@ -73,10 +73,13 @@ stap_status check_solvable(const stap_problem* q) {
 stap_status hip_status(hipError_t e) { return e == hipSuccess ? STAP_OK : STAP_ERR_HIP; }
 
 // Kernel-variant table written by the autotuner: [kind][dof class][steer
-// class][precision][refine] -> variant (0 = built-in default).
+// class][precision][refine] -> variant (0 = built-in default).  Kind 0 is
+// the fused covariance -> solve of stap_run, kind 1 the stage weight solve.
 constexpr int kDofClass[] = {16, 32, 48, 64, 96, 128, 160, 192};
 constexpr int kSteerClass[] = {16, 32, 64};
-int8_t g_tune[1][8][3][3][2];
+constexpr int kKinds = 2;
+int8_t g_tune[kKinds][8][3][3][2];
+bool valid_variant(int v) { return v == 0 || v == 4 || v == 8 || v == 16 || v == 32; }
 
 int dof_class(int d) {
   for (int i = 0; i < 8; ++i)
@@ -88,11 +91,22 @@ int steer_class(int s) {
     if (s <= kSteerClass[i]) return i;
   return -1;
 }
-int fused_variant(const Dims& d) {
+int tuned(int kind, const Dims& d) {
   const int dc = dof_class(d.D), sc = steer_class(d.S);
-  if (dc < 0 || sc < 0) return 16;
-  const int v = g_tune[0][dc][sc][d.prec][d.refine > 0 ? 1 : 0];
+  if (dc < 0 || sc < 0) return 0;
+  return g_tune[kind][dc][sc][d.prec][d.refine > 0 ? 1 : 0];
+}
+int fused_variant(const Dims& d) {
+  const int v = tuned(0, d);
   return v == 0 ? 16 : v;
+}
+// Stage solve: the blocked matrix-core solve (variant 4 or 8 waves) where
+// the table asks for it and the shape allows, else the column-sweep solve.
+hipError_t stage_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
+                       hipStream_t st) {
+  const int v = tuned(1, d);
+  if ((v == 4 || v == 8) && stap::bsolve_supported(d, v)) return stap::launch_bsolve(d, cov, steer, w, info, st, v);
+  return stap::launch_solve(d, cov, steer, w, info, st);
 }
 
 constexpr size_t kAlign = 256;
@@ -175,9 +189,8 @@ stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov, c
   if (!aligned(cov, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
   if ((s = check_solvable(prob)) != STAP_OK) return s;
   const Dims d = dims_of(prob);
-  return hip_status(stap::launch_solve(d, reinterpret_cast<const float2*>(cov),
-                                       reinterpret_cast<const float2*>(steer), reinterpret_cast<float2*>(w),
-                                       info, (hipStream_t)stream));
+  return hip_status(stage_solve(d, reinterpret_cast<const float2*>(cov), reinterpret_cast<const float2*>(steer),
+                                 reinterpret_cast<float2*>(w), info, (hipStream_t)stream));
 }
 
 stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap, const stap_cf32* steer,
@@ -271,7 +284,7 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
         if (e == hipSuccess) e = stap::launch_fused(d, pd.snap, pd.steer, pd.w, pd.info, st, fused_variant(d));
       } else {
         if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);
-        if (e == hipSuccess) e = stap::launch_solve(d, cov, pd.steer, pd.w, pd.info, st);
+        if (e == hipSuccess) e = stage_solve(d, cov, pd.steer, pd.w, pd.info, st);
       }
       if (e == hipSuccess) e = stap::launch_inner(d, pd.w, pd.snap, pd.power, nullptr, st);
       if (e != hipSuccess) return STAP_ERR_HIP;
@@ -391,15 +404,16 @@ const char* stap_status_string(stap_status status) {
 stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine,
                           int32_t variant) {
   const int dc = dof_class(dof), sc = steer_class(n_steer);
-  if (kind != 0 || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0) return STAP_ERR_ARG;
-  if (variant != 0 && variant != 16 && variant != 32) return STAP_ERR_ARG;
+  if (kind < 0 || kind >= kKinds || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0)
+    return STAP_ERR_ARG;
+  if (!valid_variant(variant)) return STAP_ERR_ARG;
   g_tune[kind][dc][sc][precision][refine > 0 ? 1 : 0] = (int8_t)variant;
   return STAP_OK;
 }
 
 int32_t stap_tune_get(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine) {
   const int dc = dof_class(dof), sc = steer_class(n_steer);
-  if (kind != 0 || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0) return -1;
+  if (kind < 0 || kind >= kKinds || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0) return -1;
   return g_tune[kind][dc][sc][precision][refine > 0 ? 1 : 0];
 }
 

@@ -1,0 +1,11 @@
+// Fused covariance -> blocked matrix-core solve, FP32, batched covariance products.
+#include "bfused_launch.h"
+
+namespace stap {
+
+hipError_t launch_bfused_batched_f32(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer,
+                                    int waves, hipStream_t st) {
+  return bfused::batched<0>(desc, n, total, max_dof, max_steer, waves, st);
+}
+
+}  // namespace stap

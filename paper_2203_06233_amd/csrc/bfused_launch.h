@@ -1,0 +1,78 @@
+// Launch helpers of the fused covariance -> blocked matrix-core solve
+// (fused_impl.h, bsolve_impl.h): dispatch over the covariance block columns,
+// the steering class and the wave count.  Included by one translation unit
+// per (precision, single or batched) so the instantiations build in
+// parallel.  No refinement on this path.
+#pragma once
+
+#include <type_traits>
+
+#include "fused_impl.h"
+
+namespace stap {
+namespace bfused {
+
+
+// register blocks per wave for NB block columns and NS steering blocks
+constexpr int nslot(int NB, int NS, int NW) { return (NB * (NB + 1) / 2 + NS * NB + NW - 1) / NW; }
+
+template <int NB, int NS, int NW, int MODE>
+hipError_t go1(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info, hipStream_t st) {
+  hipLaunchKernelGGL((bfused_kernel<NB, nslot(NB, NS, NW), NW, MODE>), dim3(d.P * d.B), dim3(64 * NW), 0, st,
+                     snap, steer, w, info, d);
+  return hipGetLastError();
+}
+
+template <int NB, int NS, int NW, int MODE>
+hipError_t gob(const ProbDesc* desc, int n, long long total, hipStream_t st) {
+  // enough workgroups to fill every CU a few times over, never more than systems
+  const long long want = 256LL * (NW == 4 ? 4 : 2);
+  const dim3 grid((unsigned)(total < want ? total : want)), block(64 * NW);
+  hipLaunchKernelGGL((bfused_batched_kernel<NB, nslot(NB, NS, NW), NW, MODE>), grid, block, 0, st, desc, n,
+                     total);
+  return hipGetLastError();
+}
+
+// one switch for the single-cube and batched launches
+template <int MODE, class F>
+hipError_t pick(int D, int S, int waves, F&& f) {
+  const int nb = (D + 15) / 16;
+  const int ns = S <= 16 ? 1 : S <= 32 ? 2 : 4;
+  auto by_s = [&](auto nbc, auto nwc) -> hipError_t {
+    constexpr int NB = decltype(nbc)::value, NW = decltype(nwc)::value;
+    if (ns == 1) return f(std::integral_constant<int, NB>{}, std::integral_constant<int, 1>{}, nwc);
+    if (ns == 2) return f(std::integral_constant<int, NB>{}, std::integral_constant<int, 2>{}, nwc);
+    return f(std::integral_constant<int, NB>{}, std::integral_constant<int, 4>{}, nwc);
+  };
+  using W4 = std::integral_constant<int, 4>;
+  using W8 = std::integral_constant<int, 8>;
+  switch (nb) {
+    case 1: return by_s(std::integral_constant<int, 1>{}, W4{});
+    case 2: return by_s(std::integral_constant<int, 2>{}, W4{});
+    case 3: return by_s(std::integral_constant<int, 3>{}, W4{});
+    case 4: return by_s(std::integral_constant<int, 4>{}, W4{});
+    case 5: case 6:
+      return waves == 8 ? by_s(std::integral_constant<int, 6>{}, W8{}) : by_s(std::integral_constant<int, 6>{}, W4{});
+    case 7: case 8: return by_s(std::integral_constant<int, 8>{}, W8{});
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int MODE>
+hipError_t single(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info, hipStream_t st,
+                  int waves) {
+  return pick<MODE>(d.D, d.S, waves, [&](auto nb, auto ns, auto nw) {
+    return go1<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(d, snap, steer, w, info, st);
+  });
+}
+
+template <int MODE>
+hipError_t batched(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer, int waves,
+                   hipStream_t st) {
+  return pick<MODE>(max_dof, max_steer, waves, [&](auto nb, auto ns, auto nw) {
+    return gob<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(desc, n, total, st);
+  });
+}
+
+}  // namespace bfused
+}  // namespace stap

@@ -1,0 +1,439 @@
+// Blocked Cholesky solve of one system on the FP32 matrix cores.
+//
+// The loaded covariance R_L (D x D, padded to 16 NB with an identity tail)
+// and the conjugated steering rows M = V^H (S x D, padded to 16 NS rows with
+// zeros) are cut into 16 x 16 complex blocks.  Each block lives in the
+// registers of one wave for the whole solve (static round-robin ownership),
+// so the right-looking updates never move the block they update; only the
+// operands of a step pass through LDS.
+//
+//   factorisation  for each block column J: the owner of the diagonal block
+//                  factors it (16 sequential columns inside one wave) and
+//                  forms its triangular inverse Linv_JJ; the owners of the
+//                  panel blocks form L_IJ = A_IJ Linv_JJ^H (and M_NJ :=
+//                  M_NJ Linv_JJ^H, the forward solve riding along as extra
+//                  rows); every later block X takes X -= P Q^H with P, Q
+//                  from the published panel.  M ends as Y^H = (L^-1 V)^H.
+//   gamma          gamma_s = ||y_s||^2.
+//   back solve     in row form Z L = Y^H with Z = U^H: for J descending,
+//                  Z_J = M_J Linv_JJ, then M_I -= Z_J L_JI for I < J.
+//   output         w_s = u_s / sqrt(gamma_s), u_s = conj(row s of Z).
+//
+// Block products are 16 x 16 x 16 complex, four real 16 x 16 x 4 MFMAs per
+// k-quarter.  Fragment layout (lane l, m = l % 16, q = l / 16): the lane holds
+// X[m][4q + i], i = 0..3.  This is the MFMA result layout of X^T, and the A
+// and B operand layouts of a product whose k index runs over the block
+// columns, so every product is formed transposed (X^T -= conj(Q) P^T) and no
+// block is ever shuffled.  In LDS a block keeps the same order (lane-major,
+// 32 bytes per lane), so a fragment load is two 16-byte reads per lane with
+// consecutive lanes on consecutive addresses.
+#pragma once
+
+#include "common.h"
+
+namespace stap {
+
+struct Frag {
+  float2 v[4];
+};
+struct Acc {
+  floatx4 re, im;
+};
+
+// Complex offset of element (r, c) of a block stored in fragment order.
+__device__ __forceinline__ int bofs(int r, int c) { return 4 * r + 64 * (c >> 2) + (c & 3); }
+
+__device__ __forceinline__ Frag frag_load(const float2* blk) {
+  const int l = threadIdx.x & 63;
+  const float4* p = reinterpret_cast<const float4*>(blk + 4 * l);
+  const float4 a = p[0], b = p[1];
+  Frag f;
+  f.v[0] = make_float2(a.x, a.y);
+  f.v[1] = make_float2(a.z, a.w);
+  f.v[2] = make_float2(b.x, b.y);
+  f.v[3] = make_float2(b.z, b.w);
+  return f;
+}
+__device__ __forceinline__ void frag_store(float2* blk, const Frag& f) {
+  const int l = threadIdx.x & 63;
+  float4* p = reinterpret_cast<float4*>(blk + 4 * l);
+  p[0] = make_float4(f.v[0].x, f.v[0].y, f.v[1].x, f.v[1].y);
+  p[1] = make_float4(f.v[2].x, f.v[2].y, f.v[3].x, f.v[3].y);
+}
+// Store X^T: the lane's X[m][4q + i] goes to element (4q + i, m).
+__device__ __forceinline__ void frag_store_t(float2* blk, const Frag& f) {
+  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) blk[bofs(4 * q + i, m)] = f.v[i];
+}
+__device__ __forceinline__ Frag to_frag(const Acc& a) {
+  Frag f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f.v[i] = make_float2(a.re[i], a.im[i]);
+  return f;
+}
+__device__ __forceinline__ Acc to_acc(const Frag& f) {
+  Acc a;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    a.re[i] = f.v[i].x;
+    a.im[i] = f.v[i].y;
+  }
+  return a;
+}
+__device__ __forceinline__ Acc acc_zero() {
+  Acc a;
+  a.re = floatx4{0.f, 0.f, 0.f, 0.f};
+  a.im = floatx4{0.f, 0.f, 0.f, 0.f};
+  return a;
+}
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// x -= P Q^H (SUB) or x += P Q^H.  As x^T -/+= conj(Q) P^T: MFMA A operand
+// conj(Q)[m][k], B operand P[m][k], k-quarter s covering k = 4 q' + s.
+template <bool SUB>
+__device__ __forceinline__ void mma_pqh(Acc& x, const Frag& P, const Frag& Q) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float qr = SUB ? -Q.v[s].x : Q.v[s].x, qi = SUB ? -Q.v[s].y : Q.v[s].y;
+    const float pr = P.v[s].x, pi = P.v[s].y;
+    x.re = mfma4(qr, pr, x.re);  // Re(conj(q) p) = qr pr + qi pi
+    x.re = mfma4(qi, pi, x.re);
+    x.im = mfma4(qr, pi, x.im);  // Im(conj(q) p) = qr pi - qi pr
+    x.im = mfma4(-qi, pr, x.im);
+  }
+}
+
+// x -= P Q (SUB) or x += P Q, with Qt the fragment of Q^T.  As x^T -/+= Q^T P^T.
+template <bool SUB>
+__device__ __forceinline__ void mma_pq(Acc& x, const Frag& P, const Frag& Qt) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const float qr = SUB ? -Qt.v[s].x : Qt.v[s].x, qi = SUB ? -Qt.v[s].y : Qt.v[s].y;
+    const float pr = P.v[s].x, pi = P.v[s].y;
+    x.re = mfma4(qr, pr, x.re);  // Re(q p) = qr pr - qi pi
+    x.re = mfma4(-qi, pi, x.re);
+    x.im = mfma4(qr, pi, x.im);  // Im(q p) = qr pi + qi pr
+    x.im = mfma4(qi, pr, x.im);
+  }
+}
+
+__device__ __forceinline__ float2 shfl2(float2 v, int src) {
+  return make_float2(__shfl(v.x, src), __shfl(v.y, src));
+}
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Broadcast lane J of every 16-lane row to the whole row (DPP row_newbcast).
+template <int J>
+__device__ __forceinline__ float rowb(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xF, 0xF, false));
+}
+template <int J>
+__device__ __forceinline__ float2 rowb2(float2 v) {
+  return make_float2(rowb<J>(v.x), rowb<J>(v.y));
+}
+
+// Column j of the in-wave factorisation of diag_factor_inv().
+template <int j>
+__device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, int q, int& fail) {
+  constexpr int jq = j >> 2, ji = j & 3;
+  const float piv = bcast(A.v[ji].x, j + 16 * jq);
+  if (!(piv > 0.f)) {
+    fail = j + 1;
+    return;
+  }
+  const float rs = __builtin_amdgcn_rsqf(piv);
+  const float2 amj = shfl2(A.v[ji], m + 16 * jq);  // A[m][j]
+  const float2 lm = (m > j) ? make_float2(amj.x * rs, amj.y * rs) : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = 4 * q + t;
+    const float2 rj = rowb2<j>(A.v[t]);  // A[j][c] = conj(A[c][j])
+    const float2 xj = rowb2<j>(X.v[t]);  // X[j][c]
+    const float2 g = (c > j) ? make_float2(rj.x * rs, rj.y * rs) : make_float2(0.f, 0.f);  // conj(l_cj)
+    const float2 xs = make_float2(xj.x * rs, xj.y * rs);
+    // A[m][c] -= l_mj conj(l_cj);  X[m][c] -= l_mj X[j][c] / d_j
+    A.v[t].x = fmaf(-lm.x, g.x, fmaf(lm.y, g.y, A.v[t].x));
+    A.v[t].y = fmaf(-lm.x, g.y, fmaf(-lm.y, g.x, A.v[t].y));
+    X.v[t].x = fmaf(-lm.x, xs.x, fmaf(lm.y, xs.y, X.v[t].x));
+    X.v[t].y = fmaf(-lm.x, xs.y, fmaf(-lm.y, xs.x, X.v[t].y));
+    if (m == j) X.v[t] = xs;
+  }
+}
+template <int j>
+__device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, int q, int& fail) {
+  diag_col<j>(A, X, m, q, fail);
+  if constexpr (j < 15) {
+    if (!fail) diag_cols<j + 1>(A, X, m, q, fail);
+  }
+}
+
+// Factor the Hermitian 16 x 16 block A (full, both triangles) as L L^H inside
+// one wave and return X = L^-1 (lower triangular).  Column j: pivot
+// d_j = sqrt(A[j][j]), l_mj = A[m][j] / d_j for m > j, then
+// A[m][c] -= l_mj conj(l_cj) for m, c > j; the inverse is accumulated as
+// X <- L_j^-1 X with L_j the identity carrying column j of L (row j of X
+// divided by d_j, then row m -= l_mj row j).  A[c][j] is read as conj(A[j][c])
+// from row j, which lives in the same 16-lane row of the wave (a DPP
+// broadcast); only l_mj crosses rows.  Returns 0 or the 1-based index of the
+// first non-positive pivot.
+__device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X) {
+  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
+  int fail = 0;
+  diag_cols<0>(A, X, m, q, fail);
+  return fail;
+}
+
+// Static layout of one system with NB block columns of R_L and NS block rows
+// of steering vectors (both run-time), NW waves and NSLOT register blocks per
+// wave (compile time).  Blocks are numbered column by column (the L blocks of
+// column J from the diagonal down, then the M blocks of column J), and block
+// g belongs to wave g % NW, register slot g / NW; the blocks still active at a
+// step are a suffix of this order, so round-robin keeps every step balanced
+// to within one block per wave.  Every loop over a wave's blocks runs over
+// its NSLOT slots (unrolled, so register indices are constants) and tests
+// the slot's block coordinates, which are run-time values.
+template <int NSLOT_, int NW_>
+struct BCfg {
+  static constexpr int NSLOT = NSLOT_, NW = NW_;
+  static constexpr int NT = 64 * NW;
+  // blocks a (NB, NS) system needs per wave
+  __host__ __device__ static constexpr int slots(int NB, int NS) {
+    return (NB * (NB + 1) / 2 + NS * NB + NW - 1) / NW;
+  }
+  // LDS: NB + NS + 1 exchange blocks, the gamma partials [NB][16 NS], a flag
+  __host__ __device__ static constexpr size_t lds_bytes(int NB, int NS) {
+    return (size_t)(NB + NS + 1) * 256 * 8 + (size_t)NB * 16 * NS * 4 + 16;
+  }
+};
+
+// The register slot holding diagonal block Jd in this wave, or -1.
+template <int NSLOT>
+__device__ __forceinline__ int bs_diag_slot(const int (&kind)[NSLOT], const int (&row)[NSLOT],
+                                            const int (&col)[NSLOT], int Jd) {
+  int td = -1;
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t)
+    if (kind[t] == 1 && row[t] == Jd && col[t] == Jd) td = t;
+  return td;
+}
+
+// Factor diagonal block Jd held in slot td (after its last update from the
+// panel L_{Jd,Jd-1} in xb when `update`), keep Linv in the slot, publish it
+// at dinv and the pivot status at sflag.  The block passes through dinv on
+// its way in and out of the register slot, so the diagonal code exists once
+// and every register slot is addressed by a constant index.
+template <int NSLOT>
+__device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSLOT], int td, int Jd, bool update, const float2* xb,
+                                               float2* dinv, int* sflag) {
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t)
+    if (td == t) frag_store(dinv, to_frag(acc[t]));
+  Frag A = frag_load(dinv), X;
+  if (update) {
+    Acc a = to_acc(A);
+    const Frag P = frag_load(xb + Jd * 256);
+    mma_pqh<true>(a, P, P);
+    A = to_frag(a);
+  }
+  const int f = diag_factor_inv(A, X);
+  frag_store(dinv, X);
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t)
+    if (td == t) acc[t] = to_acc(X);
+  if ((threadIdx.x & 63) == 0) *sflag = f ? 16 * Jd + f : 0;
+}
+
+// Solve one system (D <= 16 NB, S <= 16 NS, slots(NB, NS) <= NSLOT).
+// src.lower(i, k) (k <= i < D) yields the loaded covariance; lds points at
+// lds_bytes(NB, NS) of 16-byte aligned LDS, which may hold the source itself
+// (it is read completely before the first write).  W is this system's [S][D]
+// output, info its status word (may be null).
+template <class C, class RSrc>
+__device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __restrict__ steer,
+                                              float2* __restrict__ W, int* __restrict__ info, const Dims& d,
+                                              unsigned char* lds) {
+  constexpr int NSLOT = C::NSLOT, NW = C::NW;
+  const int D = d.D, S = d.S;
+  const int NB = (D + 15) >> 4, NS = (S + 15) >> 4;
+  float2* xb = reinterpret_cast<float2*>(lds);  // exchange blocks, 256 complex each
+  float* gpart = reinterpret_cast<float*>(lds + (size_t)(NB + NS + 1) * 256 * 8);
+  int* sflag = reinterpret_cast<int*>(gpart + NB * 16 * NS);
+  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, q = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  // block coordinates of each slot: kind 0 none, 1 L block (row I), 2 M
+  // block (row N); col = block column
+  int kind[NSLOT], row[NSLOT], col[NSLOT];
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t) {
+    const int g = wave + NW * t;
+    kind[t] = 0;
+    row[t] = 0;
+    col[t] = 0;
+    int start = 0;
+    for (int J = 0; J < NB; ++J) {
+      const int len = NB - J + NS;
+      if (g >= start && g < start + len) {
+        const int o = g - start;
+        col[t] = J;
+        kind[t] = o < NB - J ? 1 : 2;
+        row[t] = o < NB - J ? J + o : o - (NB - J);
+      }
+      start += len;
+    }
+  }
+
+  Acc acc[NSLOT];
+  // ---- load R_L blocks (identity beyond D) and M = V^H blocks
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t) {
+    Acc a = acc_zero();
+    if (kind[t] == 1) {
+      const int r = 16 * row[t] + m;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int c = 16 * col[t] + 4 * q + i;
+        float2 v;
+        if (r < D && c < D) {
+          if (c <= r) {
+            v = src.lower(r, c);
+          } else {
+            v = src.lower(c, r);
+            v.y = -v.y;
+          }
+        } else {
+          v = make_float2(r == c ? 1.f : 0.f, 0.f);
+        }
+        a.re[i] = v.x;
+        a.im[i] = v.y;
+      }
+    } else if (kind[t] == 2) {
+      const int s = 16 * row[t] + m;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 16 * col[t] + 4 * q + i;
+        const float2 v = (s < S && k < D) ? steer[s * D + k] : make_float2(0.f, 0.f);
+        a.re[i] = v.x;
+        a.im[i] = -v.y;
+      }
+    }
+    acc[t] = a;
+  }
+  __syncthreads();  // the source may be LDS that the exchange blocks reuse
+
+  // ---- factorisation with the forward solve of the steering rows.  The
+  // wave owning diagonal block J+1 applies its last update (from column J)
+  // first and factors it right away, while the other waves finish the
+  // updates of step J, so only the first diagonal block is factored with
+  // every other wave waiting.
+  float2* dinv = xb + (size_t)(NB + NS) * 256;
+  // step J = -1 only factors diagonal block 0
+  int fail = 0;
+  for (int J = -1; J < NB; ++J) {
+    if (J >= 0) {
+      __syncthreads();
+      fail = *sflag;
+      if (fail) break;
+      const Frag Q = frag_load(dinv);
+#pragma unroll
+      for (int t = 0; t < NSLOT; ++t) {
+        if (kind[t] != 0 && col[t] == J && !(kind[t] == 1 && row[t] == J)) {
+          const Frag P = to_frag(acc[t]);
+          Acc x = acc_zero();
+          mma_pqh<false>(x, P, Q);
+          acc[t] = x;
+          frag_store(xb + (kind[t] == 1 ? row[t] : NB + row[t]) * 256, to_frag(x));
+        }
+      }
+      __syncthreads();
+    }
+    const int tn = J + 1 < NB ? bs_diag_slot<NSLOT>(kind, row, col, J + 1) : -1;
+    if (tn >= 0) bs_factor_diag<NSLOT>(acc, tn, J + 1, J >= 0, xb, dinv, sflag);
+    if (J >= 0) {
+#pragma unroll
+      for (int t = 0; t < NSLOT; ++t) {
+        if (kind[t] != 0 && col[t] > J && t != tn) {
+          const Frag P = frag_load(xb + (kind[t] == 1 ? row[t] : NB + row[t]) * 256);
+          const Frag Q = frag_load(xb + col[t] * 256);
+          mma_pqh<true>(acc[t], P, Q);
+        }
+      }
+    }
+  }
+
+  if (fail) {
+    for (int e = tid; e < S * D; e += C::NT) W[e] = make_float2(0.f, 0.f);
+    if (tid == 0 && info) *info = fail;
+    return;
+  }
+
+  // ---- gamma_s = ||y_s||^2, partial per block column in a fixed order
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t) {
+    if (kind[t] == 2) {
+      float p = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) p = fmaf(acc[t].re[i], acc[t].re[i], fmaf(acc[t].im[i], acc[t].im[i], p));
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      if (q == 0) gpart[col[t] * 16 * NS + 16 * row[t] + m] = p;
+    }
+  }
+
+  // ---- back solve, row form Z L = Y^H
+  float2* zb = xb + (size_t)NB * 256;
+  for (int J = NB - 1; J >= 0; --J) {
+    __syncthreads();  // previous readers of the exchange blocks are done
+#pragma unroll
+    for (int t = 0; t < NSLOT; ++t)  // L_JI^T (Linv_JJ^T at I = J)
+      if (kind[t] == 1 && row[t] == J) frag_store_t(xb + col[t] * 256, to_frag(acc[t]));
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NSLOT; ++t) {
+      if (kind[t] == 2 && col[t] == J) {
+        const Frag P = to_frag(acc[t]);
+        Acc x = acc_zero();
+        mma_pq<false>(x, P, frag_load(xb + J * 256));
+        acc[t] = x;
+        frag_store(zb + row[t] * 256, to_frag(x));
+      }
+    }
+    if (J > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NSLOT; ++t)
+        if (kind[t] == 2 && col[t] < J)
+          mma_pq<true>(acc[t], frag_load(zb + row[t] * 256), frag_load(xb + col[t] * 256));
+    }
+  }
+  __syncthreads();  // gamma partials
+
+  // ---- w_s = u_s / sqrt(gamma_s), u_s = conj(z_s)
+#pragma unroll
+  for (int t = 0; t < NSLOT; ++t) {
+    if (kind[t] == 2) {
+      const int s = 16 * row[t] + m;
+      float gam = 0.f;
+      for (int J = 0; J < NB; ++J) gam += gpart[J * 16 * NS + s];
+      const float sc = 1.f / sqrtf(gam);
+      if (s < S) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = 16 * col[t] + 4 * q + i;
+          if (k < D) W[s * D + k] = make_float2(acc[t].re[i] * sc, -acc[t].im[i] * sc);
+        }
+      }
+    }
+  }
+  if (tid == 0 && info) *info = 0;
+}
+
+}  // namespace stap

@@ -10,6 +10,7 @@
 // through HBM (P*B*D*D*8 bytes written and half of it read back).
 #pragma once
 
+#include "bsolve_impl.h"
 #include "common.h"
 #include "cov_impl.h"
 #include "kernels.h"
@@ -30,7 +31,7 @@ __device__ __forceinline__ void fused_system(const float2* __restrict__ snap, co
                                              const Dims& d, int sys) {
   using K = SolveCfg<TY, NA, NB, NVS>;
   using C = CovCfg<K::DPC, K::NT / 64, MODE>;
-  constexpr int PACK = K::kPacked * 8;
+  constexpr int PACK = (K::kPacked + (REFINE ? K::kSlab : 0)) * 8;  // packed R_L (+ residual slab)
   constexpr int BYTES = C::LDS_BYTES > PACK ? C::LDS_BYTES : PACK;
   __shared__ __align__(16) unsigned char lds[BYTES];
   __shared__ SolveShared<K> sh;
@@ -48,7 +49,7 @@ __device__ __forceinline__ void fused_system(const float2* __restrict__ snap, co
   float2* Rp = reinterpret_cast<float2*>(lds);
   cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
   __syncthreads();
-  solve_system<K, REFINE, true>(PackedR{Rp}, Rp, steer, wout + (long long)sys * d.S * D,
+  solve_system<K, REFINE, true>(PackedR{Rp}, Rp, Rp + K::kPacked, steer, wout + (long long)sys * d.S * D,
                                 info_out ? info_out + sys : nullptr, d, sh);
 }
 
@@ -77,6 +78,63 @@ __global__ __launch_bounds__(16 * TY) void fused_batched_kernel(const ProbDesc* 
     const ProbDesc& pd = desc[lo];
     const Dims d = pd.d;
     fused_system<TY, NA, NB, NVS, MODE, REFINE>(pd.snap, pd.steer, pd.w, pd.info, d, (int)(g - pd.sys_begin));
+    __syncthreads();
+  }
+}
+
+// The same with the blocked matrix-core solve (bsolve_impl.h): NB block
+// columns of the covariance (compile time, for the covariance tiles), NW
+// waves, NSLOT register blocks per wave (enough for NB and the largest S).
+template <int NB, int NSLOT, int NW, int MODE>
+__device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, const float2* __restrict__ steer,
+                                              float2* __restrict__ wout, int* __restrict__ info_out,
+                                              const Dims& d, int sys) {
+  using C = CovCfg<16 * NB, NW, MODE>;
+  using B = BCfg<NSLOT, NW>;
+  constexpr int PACK = 16 * NB * (16 * NB + 1) / 2 * 8;
+  constexpr int EXCH = (int)B::lds_bytes(NB, 4);
+  constexpr int B1 = C::LDS_BYTES > PACK ? C::LDS_BYTES : PACK;
+  constexpr int BYTES = B1 > EXCH ? B1 : EXCH;
+  __shared__ __align__(16) unsigned char lds[BYTES];
+  __shared__ double dsum[16 * NB];
+  __shared__ float red[NW];
+  __shared__ float s_delta;
+
+  const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
+  const int D = d.D;
+  const float2* X = snap + (long long)k * D * d.R + (long long)b * d.N;
+  floatx4 accR[C::TPW], accI[C::TPW];
+  cov_accumulate<C>(X, d.R, D, d.N, lds, red, accR, accI);
+  const float dl = cov_delta<C>(accR, D, d.eps, dsum, &s_delta);
+  __syncthreads();
+  float2* Rp = reinterpret_cast<float2*>(lds);
+  cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
+  __syncthreads();
+  bsolve_system<B>(PackedR{Rp}, steer, wout + (long long)sys * d.S * D, info_out ? info_out + sys : nullptr, d,
+                   lds);
+}
+
+template <int NB, int NSLOT, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void bfused_kernel(const float2* __restrict__ snap,
+                                                         const float2* __restrict__ steer,
+                                                         float2* __restrict__ wout, int* __restrict__ info_out,
+                                                         Dims d) {
+  bfused_system<NB, NSLOT, NW, MODE>(snap, steer, wout, info_out, d, blockIdx.x);
+}
+
+template <int NB, int NSLOT, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
+                                                                 long long total) {
+  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (desc[mid].sys_begin <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProbDesc& pd = desc[lo];
+    const Dims d = pd.d;
+    bfused_system<NB, NSLOT, NW, MODE>(pd.snap, pd.steer, pd.w, pd.info, d, (int)(g - pd.sys_begin));
     __syncthreads();
   }
 }

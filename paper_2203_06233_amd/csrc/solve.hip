@@ -31,14 +31,15 @@ __global__ __launch_bounds__(16 * TY) void solve_kernel(const float2* __restrict
                                                         Dims d) {
   using K = SolveCfg<TY, NA, NB, NVS>;
   __shared__ SolveShared<K> sh;
-  extern __shared__ __align__(16) float2 dyn[];  // refinement: packed R_L
+  extern __shared__ __align__(16) float2 dyn[];  // refinement: packed R_L, residual slab
   const int sys = blockIdx.x;
   GlobalR src{cov + (long long)sys * d.D * d.D, d.D};
   if (REFINE && K::kPackedInLds) {
     for (int i = threadIdx.x / 16; i < d.D; i += TY)
       for (int k = threadIdx.x % 16; k <= i; k += 16) dyn[i * (i + 1) / 2 + k] = src.lower(i, k);
   }
-  solve_system<K, REFINE, K::kPackedInLds>(src, dyn, steer, wout + (long long)sys * d.S * d.D,
+  solve_system<K, REFINE, K::kPackedInLds>(src, dyn, dyn + (K::kPackedInLds ? K::kPacked : 0), steer,
+                                           wout + (long long)sys * d.S * d.D,
                                            info_out ? info_out + sys : nullptr, d, sh);
 }
 

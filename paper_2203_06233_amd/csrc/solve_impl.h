@@ -36,7 +36,8 @@ struct SolveCfg {
   static constexpr bool kPackedInLds = DPC <= 128;
   static constexpr int kPacked = DPC * (DPC + 1) / 2;
   __host__ __device__ static constexpr bool slot(int a, int b) { return 16 * b <= TY * a + TY - 1; }
-  static size_t refine_lds_bytes() { return (kPackedInLds ? (size_t)kPacked : 0) * sizeof(float2); }
+  static constexpr int kSlab = 16 * DPC;  // refinement residual exchange (complex values)
+  static size_t refine_lds_bytes() { return ((kPackedInLds ? (size_t)kPacked : 0) + kSlab) * sizeof(float2); }
 };
 
 template <class K>
@@ -149,12 +150,108 @@ __device__ __forceinline__ void sweep_fwd(float2 (&x)[K::NVS][K::NB], const floa
   __syncthreads();
 }
 
+// Refinement residual on the FP64 matrix cores: conj(r_s) = conj(v_s - R_L u_s)
+// into rv, for u_s held as vm = conj(u_s).  The steering vectors are taken
+// 16 at a time (a slab): the threads holding them publish u for the slab to
+// LDS as U[k][s], then each wave forms 16 x 16 output blocks (rows I) as
+// sum over K of R_L[I][K] U[K] with v_mfma_f64_16x16x4 (four real products
+// per complex one; FP32 operands converted exactly, FP64 accumulation), takes
+// r = v - R_L u in FP64, rounds it to FP32 and hands it back through the same
+// slab.  FP64 MFMA lane layout (lane l, m = l % 16, q = l / 16): A operand
+// A[m][q], B operand B[q][m], result register i holds D[q + 4i][m] (rows
+// interleaved, unlike the FP32 16 x 16 x 4 form).
+template <class K, bool RP_LDS, class RSrc>
+__device__ __forceinline__ void residual_mfma(const RSrc& src, const float2* Rp, float2* slab,
+                                              const float2 (&vm)[K::NVS][K::NB], float2 (&rv)[K::NVS][K::NB],
+                                              const float2* __restrict__ steer, int D, int S) {
+  constexpr int TY = K::TY, NB = K::NB, NVS = K::NVS, NW = K::NT / 64;
+  constexpr int NI = (NB + NW - 1) / NW;  // output row blocks per wave
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, wave = tid >> 6, m16 = lane & 15, q = lane >> 4;
+  const int nslab = (S + 15) >> 4;
+#pragma unroll
+  for (int a = 0; a < NVS; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) rv[a][b] = make_float2(0.f, 0.f);
+  // R_L[m][k] from the stored lower triangle, zero outside D x D
+  auto relem = [&](int m, int k) -> float2 {
+    const int mc = min(m, D - 1), kc = min(k, D - 1);
+    const bool lower = kc <= mc;
+    const int hi = lower ? mc : kc, lo = lower ? kc : mc;
+    float2 v = RP_LDS ? Rp[hi * (hi + 1) / 2 + lo] : src.lower(hi, lo);
+    v.y = lower ? v.y : -v.y;
+    return (m < D && k < D) ? v : make_float2(0.f, 0.f);
+  };
+  for (int N = 0; N < nslab; ++N) {
+#pragma unroll
+    for (int a = 0; a < NVS; ++a) {
+      const int s = ty + TY * a;
+      if ((s >> 4) == N) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) slab[(tx + 16 * b) * 16 + (s & 15)] = conjf2(vm[a][b]);
+      }
+    }
+    __syncthreads();
+    float2 res[NI][4];
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const int I = wave + NW * ii;
+      if (I < NB) {
+        doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+        const int m = 16 * I + m16;
+#pragma unroll 1
+        for (int kb = 0; kb < NB; ++kb) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int k = 16 * kb + 4 * s4 + q;
+            const float2 r = relem(m, k);
+            const float2 u = slab[k * 16 + m16];
+            const double ar = r.x, ai = r.y, ur = u.x, ui = u.y;
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ur, cr, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, ui, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ui, ci, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ur, ci, 0, 0, 0);
+          }
+        }
+        const int s = 16 * N + m16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = 16 * I + q + 4 * i;
+          float2 v = make_float2(0.f, 0.f);
+          if (s < S && k < D) v = steer[s * D + k];
+          res[ii][i] = make_float2((float)((double)v.x - cr[i]), (float)((double)v.y - ci[i]));
+        }
+      }
+    }
+    __syncthreads();  // every wave has read U
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const int I = wave + NW * ii;
+      if (I < NB) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) slab[(16 * I + q + 4 * i) * 16 + m16] = res[ii][i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NVS; ++a) {
+      const int s = ty + TY * a;
+      if ((s >> 4) == N) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) rv[a][b] = conjf2(slab[(tx + 16 * b) * 16 + (s & 15)]);
+      }
+    }
+    __syncthreads();  // the slab is rewritten for the next 16 steering vectors
+  }
+}
+
 // Solve one system.  src.lower(i, k) (k <= i) yields the loaded covariance;
 // with RP_LDS the refinement residual reads the same lower triangle packed
-// row-major from LDS at Rp (row i at i(i+1)/2), else through src.  W is this
-// system's [S][D] output, info its status word (may be null).
+// row-major from LDS at Rp (row i at i(i+1)/2), else through src.  slab is
+// LDS for 16 * DPC complex values (refinement only).  W is this system's
+// [S][D] output, info its status word (may be null).
 template <class K, bool REFINE, bool RP_LDS, class RSrc>
-__device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp,
+__device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, float2* slab,
                                              const float2* __restrict__ steer, float2* __restrict__ W,
                                              int* __restrict__ info, const Dims& d, SolveShared<K>& sh) {
   constexpr int TY = K::TY, NA = K::NA, NB = K::NB, NVS = K::NVS, NT = K::NT, DPC = K::DPC;
@@ -281,67 +378,8 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp,
 
   if (REFINE) {
     for (int it = 0; it < d.refine; ++it) {
-      // conj(r_s[k]) = conj(v_s[k]) - sum_q conj(R[k][q]) conj(u_s[q]) in FP64.
-      // conj(u_s[q]) for q = tx' + 16 b sits in register vm[a][b] of lane
-      // tx' of the same 16-lane group (same ty), so it is broadcast with a
-      // shuffle.  conj(R[k][q]) is the stored lower element (k, q) conjugated
-      // when q <= k, else the stored (q, k): a select, not a branch.
       float2 rv[NVS][NB];
-      int kb[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int k = min(tx + 16 * b, D - 1);
-        kb[b] = k * (k + 1) / 2;
-      }
-      auto fetch = [&](int q, int b) -> float2 {
-        const int k = tx + 16 * b;
-        const int kc = min(k, D - 1);
-        const bool lower = q <= kc;
-        float2 v;
-        if (RP_LDS) {
-          v = Rp[lower ? kb[b] + q : q * (q + 1) / 2 + kc];
-        } else {
-          v = src.lower(lower ? kc : q, lower ? q : kc);
-        }
-        v.y = lower ? -v.y : v.y;
-        return (k < D) ? v : make_float2(0.f, 0.f);
-      };
-#pragma unroll
-      for (int a = 0; a < NVS; ++a) {
-        double accr[NB], acci[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          accr[b] = 0.0;
-          acci[b] = 0.0;
-        }
-#pragma unroll
-        for (int bq = 0; bq < NB; ++bq) {
-          const int qn = min(16, D - 16 * bq);
-          for (int t = 0; t < qn; ++t) {
-            const int q = 16 * bq + t;
-            const float ur_f = __shfl(vm[a][bq].x, t, 16);
-            const float ui_f = __shfl(vm[a][bq].y, t, 16);
-            const double ur = ur_f, ui = ui_f;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              const float2 v = fetch(q, b);
-              const double rr = v.x, ri = v.y;
-              accr[b] = fma(rr, ur, fma(-ri, ui, accr[b]));
-              acci[b] = fma(rr, ui, fma(ri, ur, acci[b]));
-            }
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const int s = ty + TY * a, k = tx + 16 * b;
-          if (s < S && k < D) {
-            const float2 v = steer[s * D + k];
-            rv[a][b] = make_float2((float)((double)v.x - accr[b]), (float)(-(double)v.y - acci[b]));
-          } else {
-            rv[a][b] = make_float2(0.f, 0.f);
-          }
-        }
-      }
+      residual_mfma<K, RP_LDS>(src, Rp, slab, vm, rv, steer, D, S);
       sweep_fwd<K>(rv, lm, D, sh);
       sweep_back<K>(rv, lm, D, sh);
 #pragma unroll

@@ -1,8 +1,10 @@
 """Autotuner for the kernel variants of stap_run.
 
 For each shape class it runs stap_run on a seeded cube of that shape under
-every candidate variant of the fused covariance->solve kernel (16 x 16 or
-32 x 16 thread grid per system), keeps the fastest by HIP-event time, and
+every candidate variant of the fused covariance->solve kernel (the
+column-sweep solve on a 16 x 16 or 32 x 16 thread grid per system, or the
+blocked matrix-core solve with 4 or 8 waves), keeps the fastest by HIP-event
+time, and
 stores the choice in a JSON cache keyed by GPU architecture, DOF class,
 steering class, precision and refinement.  The binding applies the cache
 (``tune_cache.json`` beside this file, or ``$STAP_TUNE_CACHE``) at import.
@@ -18,7 +20,13 @@ import sys
 
 CACHE = os.environ.get("STAP_TUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
-CANDIDATES = (16, 32)
+CANDIDATES = (16, 32, 4, 8)
+
+
+def candidates(dof, refine):
+    """Variants worth timing for a shape: the 32-row grid needs D > 32, the
+    blocked solve runs without refinement."""
+    return [v for v in CANDIDATES if not (v == 32 and dof <= 32) and not (v in (4, 8) and refine > 0)]
 
 
 def arch() -> str:
@@ -73,9 +81,7 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
     W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device=dev)
     times = {}
     ref = None
-    for v in CANDIDATES:
-        if v == 32 and wl.dof <= 32:
-            continue
+    for v in candidates(wl.dof, refine):
         stap.tune_set(wl.dof, wl.n_steer, precision, refine, v)
         for _ in range(warmup):
             runner.run([cube], [V], powers=[power], weights=[W])
@@ -94,7 +100,7 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
         else:
             rel = float((w - ref).abs().max() / ref.abs().max())
             if rel > 1e-3:
-                raise RuntimeError(f"variant {v} disagrees with variant {CANDIDATES[0]}: {rel}")
+                raise RuntimeError(f"variant {v} disagrees with the first variant timed: {rel}")
     best = min(times, key=times.get)
     stap.tune_set(wl.dof, wl.n_steer, precision, refine, best)
     return best, times

@@ -135,7 +135,9 @@ def test_tuning_table(binding):
     finally:
         binding.tune_set(96, 32, "bf16", 1, saved)
     assert lib.stap_tune_set(0, 96, 32, 1, 1, 24) == -1
-    assert lib.stap_tune_set(1, 96, 32, 1, 1, 16) == -1
+    assert lib.stap_tune_set(2, 96, 32, 1, 1, 16) == -1
+    assert lib.stap_tune_set(1, 96, 32, 1, 0, 8) == 0 and lib.stap_tune_get(1, 96, 32, 1, 0) == 8
+    assert lib.stap_tune_set(1, 96, 32, 1, 0, 0) == 0
     assert lib.stap_tune_set(0, 200, 32, 1, 1, 16) == -1
     assert lib.stap_tune_get(0, 96, 65, 1, 1) == -1
 

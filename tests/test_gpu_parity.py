@@ -7,6 +7,8 @@ Chain tests run ``stap_run`` on seeded cubes and compare with the oracle run
 on the same cube: output power normwise <= 1e-4 on the plain FP32 path;
 weights <= 1e-3 and SINR loss <= 0.1 dB on the mixed BF16 path.
 """
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -144,13 +146,40 @@ def _solve_case(wl):
     return RL32, V, Wo, Go, Io
 
 
+SOLVE_SHAPES = TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 1024, 3, 16, 16),
+                       (32, 32, 256, 3, 2, 32), (32, 32, 256, 3, 2, 64),
+                       (40, 32, 256, 3, 2, 20), (48, 32, 256, 3, 2, 20),
+                       (64, 32, 256, 3, 2, 64), (60, 32, 512, 3, 2, 33)]
+
+
+@contextlib.contextmanager
+def solve_variant(stap, kind, dof, n_steer, precision, refine, variant):
+    """Select a kernel variant in the tuning table for one shape class."""
+    saved = stap.tune_get(dof, n_steer, precision, refine, kind=kind)
+    stap.tune_set(dof, n_steer, precision, refine, variant, kind=kind)
+    try:
+        yield
+    finally:
+        stap.tune_set(dof, n_steer, precision, refine, saved, kind=kind)
+
+
 @pytest.mark.parametrize("refine", [0, 1, 2])
-@pytest.mark.parametrize("shape", TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 1024, 3, 16, 16),
-                                          (32, 32, 256, 3, 2, 32), (32, 32, 256, 3, 2, 64),
-                                          (40, 32, 256, 3, 2, 20), (48, 32, 256, 3, 2, 20),
-                                          (64, 32, 256, 3, 2, 64), (60, 32, 512, 3, 2, 33)], ids=str)
+@pytest.mark.parametrize("shape", SOLVE_SHAPES, ids=str)
 def test_solve_parity(stap, shape, refine):
+    _check_solve(stap, tiny_wl(shape), refine)
+
+
+@pytest.mark.parametrize("waves", [4, 8])
+@pytest.mark.parametrize("shape", [s for s in SOLVE_SHAPES if s[0] * s[3] <= 128], ids=str)
+def test_blocked_solve_parity(stap, shape, waves):
+    """The blocked matrix-core solve, selected through the tuning table."""
     wl = tiny_wl(shape)
+    with solve_variant(stap, 1, wl.dof, wl.n_steer, "fp32", 0, waves):
+        _check_solve(stap, wl, 0, tag=f"bsolve{waves}")
+
+
+def _check_solve(stap, wl, refine, tag="solve"):
+    shape = wl.name
     RL32, V, Wo, Go, Io = _solve_case(wl)
     w, info = stap.solve_weights(prob_of(wl, refine=refine), dev(RL32), dev(V))
     w, info = host(w), host(info)
@@ -159,7 +188,7 @@ def test_solve_parity(stap, shape, refine):
     cond = np.linalg.cond(RL32.astype(np.complex128))
     per = metrics.per_system_rel_err(w, Wo)
     bnd = 8.0 * wl.dof * cond * U32
-    _report("solve", shape=shape, refine=refine, rel=metrics.rel_err(w, Wo),
+    _report(tag, shape=shape, refine=refine, rel=metrics.rel_err(w, Wo),
             max_ratio=float((per / bnd)[ok].max()), cond=float(cond.max()))
     assert np.all(per[ok] <= bnd[ok])
     # backward error of the solve, recovered from w: gamma = (v^H w)^2, u = w sqrt(gamma)
@@ -183,8 +212,14 @@ def test_refinement_reduces_solve_error(stap):
     assert errs[2] <= errs[1] + 2e-7
 
 
-def test_solve_info_codes(stap):
+@pytest.mark.parametrize("waves", [0, 4, 8])
+def test_solve_info_codes(stap, waves):
     D, S, P = 20, 5, 32
+    with solve_variant(stap, 1, D, S, "fp32", 0, waves):
+        _check_info_codes(stap, D, S, P)
+
+
+def _check_info_codes(stap, D, S, P):
     mats, want = [], []
     for j in (0, 3, 17, 19):
         A = np.eye(D, dtype=np.complex64)
@@ -361,6 +396,38 @@ def test_batched_run_equals_single(stap, precision, refine, graphs):
         stap.use_graphs(True)
 
 
+@pytest.mark.parametrize("waves", [4, 8])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batched_blocked_equals_single(stap, precision, waves):
+    """The persistent batched covariance -> blocked matrix-core solve gives
+    each cube the single-cube blocked result (block products and reductions
+    run in the same order whatever wave owns a block)."""
+    wls = synth.uneven_batch(6)
+    cubes = [dev(synth.make_cube(w)) for w in wls]
+    Vs = [dev(synth.steering(w)) for w in wls]
+    probs = [prob_of(w, precision, 0) for w in wls]
+    classes = [(d, s) for d in (16, 32, 48, 64, 96, 128) for s in (16, 32, 64)]
+    saved = {c: stap.tune_get(c[0], c[1], precision, 0) for c in classes}
+    try:
+        for d, s in classes:
+            stap.tune_set(d, s, precision, 0, waves)
+        Ws = [torch.empty((w.n_pulse, w.n_block, w.n_steer, w.dof), dtype=torch.complex64, device="cuda")
+              for w in wls]
+        batched = [host(p) for p in stap.Runner(probs).run(cubes, Vs, weights=Ws)]
+        for i, w in enumerate(wls):
+            W1 = torch.empty_like(Ws[i])
+            single = host(stap.run([probs[i]], [cubes[i]], [Vs[i]], weights=[W1])[0])
+            assert metrics.rel_err(batched[i], single) <= 1e-6, i
+            assert metrics.rel_err(host(Ws[i]), host(W1)) <= 1e-6, i
+        o = orc.run(synth.make_cube(wls[0]), synth.steering(wls[0]), wls[0].tdof, wls[0].n_block, wls[0].load_eps)
+        we = metrics.rel_err(host(Ws[0]), o["W"])
+        _report("batched blocked", prec=precision, waves=waves, weights=we)
+        assert we <= 1e-3
+    finally:
+        for (d, s), v in saved.items():
+            stap.tune_set(d, s, precision, 0, v)
+
+
 def test_graph_replays_equal_eager(stap):
     """Replays of the cached graph, with eager work and synchronisations
     between them, all equal the eager result."""
@@ -411,15 +478,17 @@ def test_uneven_batch_64_sampled(stap):
 
 @pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 0), ("bf16", 1)])
 def test_fused_variants_match_oracle(stap, precision, refine):
-    """Both thread grids of the fused covariance->solve kernel (selected
-    through the tuning table) against the oracle on the 48-DOF cube."""
+    """Every solve variant of the fused covariance->solve kernel (the two
+    column-sweep thread grids and, without refinement, the blocked
+    matrix-core solve with 4 and 8 waves), selected through the tuning
+    table, against the oracle on the 48-DOF cube."""
     wl = synth.MEDIUM
     cube = synth.make_cube(wl)
     V = synth.steering(wl)
     o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
     out = {}
     try:
-        for variant in (16, 32):
+        for variant in (16, 32) + ((4, 8) if refine == 0 else ()):
             stap.tune_set(wl.dof, wl.n_steer, precision, refine, variant)
             prob = prob_of(wl, precision, refine)
             W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
