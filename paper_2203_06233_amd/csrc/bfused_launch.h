@@ -2,7 +2,7 @@
 // (fused_impl.h, bsolve_impl.h): dispatch over the covariance block columns,
 // the steering class and the wave count.  Included by one translation unit
 // per (precision, single or batched) so the instantiations build in
-// parallel.  No refinement on this path.
+// parallel.
 #pragma once
 
 #include <type_traits>
@@ -14,22 +14,31 @@ namespace bfused {
 
 
 // register blocks per wave for NB block columns and NS steering blocks
-constexpr int nslot(int NB, int NS, int NW) { return (NB * (NB + 1) / 2 + NS * NB + NW - 1) / NW; }
+constexpr int nsl(int NB, int NW) { return (NB * (NB + 1) / 2 + NW - 1) / NW; }
+constexpr int nsm(int NB, int NS, int NW) { return (NS * NB + NW - 1) / NW; }
 
 template <int NB, int NS, int NW, int MODE>
 hipError_t go1(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info, hipStream_t st) {
-  hipLaunchKernelGGL((bfused_kernel<NB, nslot(NB, NS, NW), NW, MODE>), dim3(d.P * d.B), dim3(64 * NW), 0, st,
-                     snap, steer, w, info, d);
+  constexpr int L = nsl(NB, NW), M = nsm(NB, NS, NW);
+  if (d.refine == 0)
+    hipLaunchKernelGGL((bfused_kernel<NB, NS, L, M, NW, MODE, false>), dim3(d.P * d.B), dim3(64 * NW), 0, st, snap, steer,
+                       w, info, d);
+  else
+    hipLaunchKernelGGL((bfused_kernel<NB, NS, L, M, NW, MODE, true>), dim3(d.P * d.B), dim3(64 * NW), 0, st, snap, steer,
+                       w, info, d);
   return hipGetLastError();
 }
 
 template <int NB, int NS, int NW, int MODE>
-hipError_t gob(const ProbDesc* desc, int n, long long total, hipStream_t st) {
+hipError_t gob(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st) {
+  constexpr int L = nsl(NB, NW), M = nsm(NB, NS, NW);
   // enough workgroups to fill every CU a few times over, never more than systems
   const long long want = 256LL * (NW == 4 ? 4 : 2);
   const dim3 grid((unsigned)(total < want ? total : want)), block(64 * NW);
-  hipLaunchKernelGGL((bfused_batched_kernel<NB, nslot(NB, NS, NW), NW, MODE>), grid, block, 0, st, desc, n,
-                     total);
+  if (refine == 0)
+    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, false>), grid, block, 0, st, desc, n, total);
+  else
+    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, true>), grid, block, 0, st, desc, n, total);
   return hipGetLastError();
 }
 
@@ -67,10 +76,10 @@ hipError_t single(const Dims& d, const float2* snap, const float2* steer, float2
 }
 
 template <int MODE>
-hipError_t batched(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer, int waves,
+hipError_t batched(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer, int refine, int waves,
                    hipStream_t st) {
   return pick<MODE>(max_dof, max_steer, waves, [&](auto nb, auto ns, auto nw) {
-    return gob<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(desc, n, total, st);
+    return gob<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(desc, n, total, refine, st);
   });
 }
 

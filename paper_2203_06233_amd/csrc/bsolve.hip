@@ -14,70 +14,76 @@ struct GlobalRB {
   __device__ float2 lower(int i, int k) const { return A[(long long)i * D + k]; }
 };
 
-template <int NSLOT, int NW>
+template <int NSL, int NSM, int NW, bool REFINE>
 __global__ __launch_bounds__(64 * NW) void bsolve_kernel(const float2* __restrict__ cov,
                                                          const float2* __restrict__ steer,
                                                          float2* __restrict__ wout, int* __restrict__ info_out,
                                                          Dims d) {
-  using C = BCfg<NSLOT, NW>;
+  using C = BCfg<NSL, NSM, NW>;
   extern __shared__ __align__(16) unsigned char lds[];
   const int sys = blockIdx.x;
-  bsolve_system<C>(GlobalRB{cov + (long long)sys * d.D * d.D, d.D}, steer, wout + (long long)sys * d.S * d.D,
-                   info_out ? info_out + sys : nullptr, d, lds);
+  bsolve_system<C, REFINE>(GlobalRB{cov + (long long)sys * d.D * d.D, d.D}, steer,
+                           wout + (long long)sys * d.S * d.D, info_out ? info_out + sys : nullptr, d, lds);
 }
 
-template <int NSLOT, int NW>
+template <int NSL, int NSM, int NW>
 hipError_t go(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info, hipStream_t st) {
-  const size_t lds = BCfg<NSLOT, NW>::lds_bytes((d.D + 15) / 16, (d.S + 15) / 16);
-  hipLaunchKernelGGL((bsolve_kernel<NSLOT, NW>), dim3(d.P * d.B), dim3(64 * NW), lds, st, cov, steer, w, info, d);
+  const size_t lds = BCfg<NSL, NSM, NW>::lds_bytes((d.D + 15) / 16, (d.S + 15) / 16);
+  if (d.refine == 0)
+    hipLaunchKernelGGL((bsolve_kernel<NSL, NSM, NW, false>), dim3(d.P * d.B), dim3(64 * NW), lds, st, cov, steer, w,
+                       info, d);
+  else
+    hipLaunchKernelGGL((bsolve_kernel<NSL, NSM, NW, true>), dim3(d.P * d.B), dim3(64 * NW), lds, st, cov, steer, w,
+                       info, d);
   return hipGetLastError();
+}
+
+template <int NW>
+int round_up(int need, const int* opts, int n) {
+  for (int i = 0; i < n; ++i)
+    if (need <= opts[i]) return opts[i];
+  return 0;
 }
 
 }  // namespace
 
-// Register blocks per wave the (D, S) shape needs with `waves` waves; the
-// instantiated slot counts are 2, 3, 4, 5, 7, 9, 12 (4 waves) and 3, 5, 7, 9
-// (8 waves).
-int bsolve_slots(int D, int S, int waves) {
-  const int NB = (D + 15) / 16, NS = (S + 15) / 16;
-  const int need = (NB * (NB + 1) / 2 + NS * NB + waves - 1) / waves;
-  static const int s4[] = {2, 3, 4, 5, 7, 9, 12}, s8[] = {3, 5, 7, 9};
+// Slot counts instantiated per wave count: L slots {1, 2, 3, 5} (4 waves) or
+// {2, 3, 5} (8 waves), M slots {1, 2, 4}.
+static const int kL4[] = {1, 2, 3, 5}, kL8[] = {2, 3, 5}, kM[] = {1, 2, 4};
+
+static bool slots_for(const Dims& d, int waves, int& nl, int& nm) {
+  const int NB = (d.D + 15) / 16, NS = (d.S + 15) / 16;
   if (waves == 4) {
-    for (int v : s4)
-      if (need <= v) return v;
+    nl = round_up<4>(BCfg<1, 1, 4>::lslots(NB), kL4, 4);
+    nm = round_up<4>(BCfg<1, 1, 4>::mslots(NB, NS), kM, 3);
   } else if (waves == 8) {
-    for (int v : s8)
-      if (need <= v) return v;
+    nl = round_up<8>(BCfg<1, 1, 8>::lslots(NB), kL8, 3);
+    nm = round_up<8>(BCfg<1, 1, 8>::mslots(NB, NS), kM, 3);
+  } else {
+    return false;
   }
-  return 0;
+  return nl > 0 && nm > 0;
 }
 
 bool bsolve_supported(const Dims& d, int waves) {
-  return d.D <= 128 && d.refine == 0 && bsolve_slots(d.D, d.S, waves) > 0;
+  int nl, nm;
+  return d.D <= 128 && slots_for(d, waves, nl, nm);
 }
 
 hipError_t launch_bsolve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                          hipStream_t st, int waves) {
-  if (!bsolve_supported(d, waves)) return hipErrorInvalidValue;
-  const int ns = bsolve_slots(d.D, d.S, waves);
-  if (waves == 4) {
-    switch (ns) {
-      case 2: return go<2, 4>(d, cov, steer, w, info, st);
-      case 3: return go<3, 4>(d, cov, steer, w, info, st);
-      case 4: return go<4, 4>(d, cov, steer, w, info, st);
-      case 5: return go<5, 4>(d, cov, steer, w, info, st);
-      case 7: return go<7, 4>(d, cov, steer, w, info, st);
-      case 9: return go<9, 4>(d, cov, steer, w, info, st);
-      case 12: return go<12, 4>(d, cov, steer, w, info, st);
-    }
-  } else {
-    switch (ns) {
-      case 3: return go<3, 8>(d, cov, steer, w, info, st);
-      case 5: return go<5, 8>(d, cov, steer, w, info, st);
-      case 7: return go<7, 8>(d, cov, steer, w, info, st);
-      case 9: return go<9, 8>(d, cov, steer, w, info, st);
-    }
-  }
+  int nl, nm;
+  if (d.D > 128 || !slots_for(d, waves, nl, nm)) return hipErrorInvalidValue;
+#define STAP_BS(L, M, W) \
+  if (nl == L && nm == M && waves == W) return go<L, M, W>(d, cov, steer, w, info, st);
+  STAP_BS(1, 1, 4) STAP_BS(1, 2, 4) STAP_BS(1, 4, 4)
+  STAP_BS(2, 1, 4) STAP_BS(2, 2, 4) STAP_BS(2, 4, 4)
+  STAP_BS(3, 1, 4) STAP_BS(3, 2, 4) STAP_BS(3, 4, 4)
+  STAP_BS(5, 1, 4) STAP_BS(5, 2, 4) STAP_BS(5, 4, 4)
+  STAP_BS(2, 1, 8) STAP_BS(2, 2, 8) STAP_BS(2, 4, 8)
+  STAP_BS(3, 1, 8) STAP_BS(3, 2, 8) STAP_BS(3, 4, 8)
+  STAP_BS(5, 1, 8) STAP_BS(5, 2, 8) STAP_BS(5, 4, 8)
+#undef STAP_BS
   return hipErrorInvalidValue;
 }
 

@@ -192,49 +192,43 @@ __device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X) {
 }
 
 // Static layout of one system with NB block columns of R_L and NS block rows
-// of steering vectors (both run-time), NW waves and NSLOT register blocks per
-// wave (compile time).  Blocks are numbered column by column (the L blocks of
-// column J from the diagonal down, then the M blocks of column J), and block
-// g belongs to wave g % NW, register slot g / NW; the blocks still active at a
-// step are a suffix of this order, so round-robin keeps every step balanced
-// to within one block per wave.  Every loop over a wave's blocks runs over
-// its NSLOT slots (unrolled, so register indices are constants) and tests
-// the slot's block coordinates, which are run-time values.
-template <int NSLOT_, int NW_>
+// of steering vectors (both run-time), NW waves, and per wave NSL register
+// slots for L blocks and NSM for M blocks (compile time).  L blocks are
+// numbered column by column from the diagonal down, M blocks column by
+// column, each set dealt round-robin to the waves (block g -> wave g % NW,
+// slot g / NW).  The blocks still active at a step are a suffix of each
+// order, so every step is balanced to within one block per wave and set.
+// Loops over a wave's blocks run over its slots (unrolled, so register
+// indices are constants) and test the slot's block coordinates, which are
+// run-time values.
+template <int NSL_, int NSM_, int NW_>
 struct BCfg {
-  static constexpr int NSLOT = NSLOT_, NW = NW_;
+  static constexpr int NSL = NSL_, NSM = NSM_, NW = NW_;
   static constexpr int NT = 64 * NW;
-  // blocks a (NB, NS) system needs per wave
-  __host__ __device__ static constexpr int slots(int NB, int NS) {
-    return (NB * (NB + 1) / 2 + NS * NB + NW - 1) / NW;
+  // L and M slots per wave a (NB, NS) system needs
+  __host__ __device__ static constexpr int lslots(int NB) { return (NB * (NB + 1) / 2 + NW - 1) / NW; }
+  __host__ __device__ static constexpr int mslots(int NB, int NS) { return (NS * NB + NW - 1) / NW; }
+  // LDS: exchange blocks (NB + NS + 1 for the factorisation and solves, all
+  // NS NB blocks of Z for the refinement residual), the gamma partials
+  // [NB][16 NS] (FP64), a flag
+  __host__ __device__ static constexpr size_t xblocks(int NB, int NS) {
+    return (size_t)(NB + NS + 1 > NS * NB ? NB + NS + 1 : NS * NB);
   }
-  // LDS: NB + NS + 1 exchange blocks, the gamma partials [NB][16 NS], a flag
   __host__ __device__ static constexpr size_t lds_bytes(int NB, int NS) {
-    return (size_t)(NB + NS + 1) * 256 * 8 + (size_t)NB * 16 * NS * 4 + 16;
+    return xblocks(NB, NS) * 256 * 8 + (size_t)NB * 16 * NS * 8 + 16;
   }
 };
 
-// The register slot holding diagonal block Jd in this wave, or -1.
-template <int NSLOT>
-__device__ __forceinline__ int bs_diag_slot(const int (&kind)[NSLOT], const int (&row)[NSLOT],
-                                            const int (&col)[NSLOT], int Jd) {
-  int td = -1;
-#pragma unroll
-  for (int t = 0; t < NSLOT; ++t)
-    if (kind[t] == 1 && row[t] == Jd && col[t] == Jd) td = t;
-  return td;
-}
-
-// Factor diagonal block Jd held in slot td (after its last update from the
+// Factor diagonal block Jd held in L slot td (after its last update from the
 // panel L_{Jd,Jd-1} in xb when `update`), keep Linv in the slot, publish it
 // at dinv and the pivot status at sflag.  The block passes through dinv on
 // its way in and out of the register slot, so the diagonal code exists once
 // and every register slot is addressed by a constant index.
-template <int NSLOT>
-__device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSLOT], int td, int Jd, bool update, const float2* xb,
+template <int NSL>
+__device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSL], int td, int Jd, bool update, const float2* xb,
                                                float2* dinv, int* sflag) {
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t)
+  for (int t = 0; t < NSL; ++t)
     if (td == t) frag_store(dinv, to_frag(acc[t]));
   Frag A = frag_load(dinv), X;
   if (update) {
@@ -246,61 +240,82 @@ __device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSLOT], int td, int Jd
   const int f = diag_factor_inv(A, X);
   frag_store(dinv, X);
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t)
+  for (int t = 0; t < NSL; ++t)
     if (td == t) acc[t] = to_acc(X);
   if ((threadIdx.x & 63) == 0) *sflag = f ? 16 * Jd + f : 0;
 }
 
-// Solve one system (D <= 16 NB, S <= 16 NS, slots(NB, NS) <= NSLOT).
-// src.lower(i, k) (k <= i < D) yields the loaded covariance; lds points at
-// lds_bytes(NB, NS) of 16-byte aligned LDS, which may hold the source itself
-// (it is read completely before the first write).  W is this system's [S][D]
+__device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// A global read the compiler must not merge with an earlier read of the
+// same address: keeping such values live across the whole solve costs more
+// registers than reading them again (they are cache hits).
+__device__ __forceinline__ float2 reload(const float2* p) {
+  const volatile float* v = reinterpret_cast<const volatile float*>(p);
+  return make_float2(v[0], v[1]);
+}
+
+// Solve one system (D <= 16 NB, S <= 16 NS, lslots(NB) <= NSL,
+// mslots(NB, NS) <= NSM).  src.lower(i, k) (k <= i < D) yields the loaded
+// covariance; it must stay readable for the whole call when REFINE (the FP64
+// residual reads it again).  xlds points at lds_bytes(NB, NS) of 16-byte
+// aligned LDS, which may overlap the source only without REFINE (the source
+// is read completely before the first write).  W is this system's [S][D]
 // output, info its status word (may be null).
-template <class C, class RSrc>
+template <class C, bool REFINE, class RSrc>
 __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __restrict__ steer,
                                               float2* __restrict__ W, int* __restrict__ info, const Dims& d,
-                                              unsigned char* lds) {
-  constexpr int NSLOT = C::NSLOT, NW = C::NW;
+                                              unsigned char* xlds) {
+  constexpr int NSL = C::NSL, NSM = C::NSM, NW = C::NW;
   const int D = d.D, S = d.S;
   const int NB = (D + 15) >> 4, NS = (S + 15) >> 4;
-  float2* xb = reinterpret_cast<float2*>(lds);  // exchange blocks, 256 complex each
-  float* gpart = reinterpret_cast<float*>(lds + (size_t)(NB + NS + 1) * 256 * 8);
+  float2* xb = reinterpret_cast<float2*>(xlds);  // exchange blocks, 256 complex each
+  double* gpart = reinterpret_cast<double*>(xlds + C::xblocks(NB, NS) * 256 * 8);
   int* sflag = reinterpret_cast<int*>(gpart + NB * 16 * NS);
   const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  float2* dinv = xb + (size_t)(NB + NS) * 256;
 
-  // block coordinates of each slot: kind 0 none, 1 L block (row I), 2 M
-  // block (row N); col = block column
-  int kind[NSLOT], row[NSLOT], col[NSLOT];
+  // block coordinates of each slot
+  bool lv[NSL], mv[NSM];
+  int lr[NSL], lc[NSL], mr[NSM], mc[NSM];
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t) {
+  for (int t = 0; t < NSL; ++t) {
     const int g = wave + NW * t;
-    kind[t] = 0;
-    row[t] = 0;
-    col[t] = 0;
+    lv[t] = false;
+    lr[t] = 0;
+    lc[t] = 0;
     int start = 0;
     for (int J = 0; J < NB; ++J) {
-      const int len = NB - J + NS;
+      const int len = NB - J;
       if (g >= start && g < start + len) {
-        const int o = g - start;
-        col[t] = J;
-        kind[t] = o < NB - J ? 1 : 2;
-        row[t] = o < NB - J ? J + o : o - (NB - J);
+        lv[t] = true;
+        lc[t] = J;
+        lr[t] = J + (g - start);
       }
       start += len;
     }
   }
+#pragma unroll
+  for (int t = 0; t < NSM; ++t) {
+    const int g = wave + NW * t;
+    mv[t] = g < NS * NB;
+    mc[t] = g / NS;
+    mr[t] = g - (g / NS) * NS;
+  }
 
-  Acc acc[NSLOT];
+  Acc al[NSL], am[NSM];
   // ---- load R_L blocks (identity beyond D) and M = V^H blocks
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t) {
+  for (int t = 0; t < NSL; ++t) {
     Acc a = acc_zero();
-    if (kind[t] == 1) {
-      const int r = 16 * row[t] + m;
+    if (lv[t]) {
+      const int r = 16 * lr[t] + m;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int c = 16 * col[t] + 4 * q + i;
+        const int c = 16 * lc[t] + 4 * q + i;
         float2 v;
         if (r < D && c < D) {
           if (c <= r) {
@@ -315,27 +330,30 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
         a.re[i] = v.x;
         a.im[i] = v.y;
       }
-    } else if (kind[t] == 2) {
-      const int s = 16 * row[t] + m;
+    }
+    al[t] = a;
+  }
+#pragma unroll
+  for (int t = 0; t < NSM; ++t) {
+    Acc a = acc_zero();
+    if (mv[t]) {
+      const int s = 16 * mr[t] + m;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int k = 16 * col[t] + 4 * q + i;
+        const int k = 16 * mc[t] + 4 * q + i;
         const float2 v = (s < S && k < D) ? steer[s * D + k] : make_float2(0.f, 0.f);
         a.re[i] = v.x;
         a.im[i] = -v.y;
       }
     }
-    acc[t] = a;
+    am[t] = a;
   }
-  __syncthreads();  // the source may be LDS that the exchange blocks reuse
+  __syncthreads();  // without REFINE the source may be LDS that the exchange blocks reuse
 
   // ---- factorisation with the forward solve of the steering rows.  The
   // wave owning diagonal block J+1 applies its last update (from column J)
   // first and factors it right away, while the other waves finish the
-  // updates of step J, so only the first diagonal block is factored with
-  // every other wave waiting.
-  float2* dinv = xb + (size_t)(NB + NS) * 256;
-  // step J = -1 only factors diagonal block 0
+  // updates of step J; step J = -1 only factors diagonal block 0.
   int fail = 0;
   for (int J = -1; J < NB; ++J) {
     if (J >= 0) {
@@ -344,28 +362,41 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
       if (fail) break;
       const Frag Q = frag_load(dinv);
 #pragma unroll
-      for (int t = 0; t < NSLOT; ++t) {
-        if (kind[t] != 0 && col[t] == J && !(kind[t] == 1 && row[t] == J)) {
-          const Frag P = to_frag(acc[t]);
+      for (int t = 0; t < NSL; ++t) {
+        if (lv[t] && lc[t] == J && lr[t] != J) {
+          const Frag P = to_frag(al[t]);
           Acc x = acc_zero();
           mma_pqh<false>(x, P, Q);
-          acc[t] = x;
-          frag_store(xb + (kind[t] == 1 ? row[t] : NB + row[t]) * 256, to_frag(x));
+          al[t] = x;
+          frag_store(xb + lr[t] * 256, to_frag(x));
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t] && mc[t] == J) {
+          const Frag P = to_frag(am[t]);
+          Acc x = acc_zero();
+          mma_pqh<false>(x, P, Q);
+          am[t] = x;
+          frag_store(xb + (NB + mr[t]) * 256, to_frag(x));
         }
       }
       __syncthreads();
     }
-    const int tn = J + 1 < NB ? bs_diag_slot<NSLOT>(kind, row, col, J + 1) : -1;
-    if (tn >= 0) bs_factor_diag<NSLOT>(acc, tn, J + 1, J >= 0, xb, dinv, sflag);
+    int tn = -1;
+#pragma unroll
+    for (int t = 0; t < NSL; ++t)
+      if (J + 1 < NB && lv[t] && lr[t] == J + 1 && lc[t] == J + 1) tn = t;
+    if (tn >= 0) bs_factor_diag<NSL>(al, tn, J + 1, J >= 0, xb, dinv, sflag);
     if (J >= 0) {
 #pragma unroll
-      for (int t = 0; t < NSLOT; ++t) {
-        if (kind[t] != 0 && col[t] > J && t != tn) {
-          const Frag P = frag_load(xb + (kind[t] == 1 ? row[t] : NB + row[t]) * 256);
-          const Frag Q = frag_load(xb + col[t] * 256);
-          mma_pqh<true>(acc[t], P, Q);
-        }
-      }
+      for (int t = 0; t < NSL; ++t)
+        if (lv[t] && lc[t] > J && t != tn)
+          mma_pqh<true>(al[t], frag_load(xb + lr[t] * 256), frag_load(xb + lc[t] * 256));
+#pragma unroll
+      for (int t = 0; t < NSM; ++t)
+        if (mv[t] && mc[t] > J)
+          mma_pqh<true>(am[t], frag_load(xb + (NB + mr[t]) * 256), frag_load(xb + mc[t] * 256));
     }
   }
 
@@ -375,60 +406,201 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
     return;
   }
 
-  // ---- gamma_s = ||y_s||^2, partial per block column in a fixed order
+  // ---- gamma_s = ||y_s||^2 (no refinement), partial per block column
+  if (!REFINE || d.refine == 0) {
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t) {
-    if (kind[t] == 2) {
-      float p = 0.f;
+    for (int t = 0; t < NSM; ++t) {
+      if (mv[t]) {
+        float p = 0.f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) p = fmaf(acc[t].re[i], acc[t].re[i], fmaf(acc[t].im[i], acc[t].im[i], p));
-      p += __shfl_xor(p, 16);
-      p += __shfl_xor(p, 32);
-      if (q == 0) gpart[col[t] * 16 * NS + 16 * row[t] + m] = p;
+        for (int i = 0; i < 4; ++i) p = fmaf(am[t].re[i], am[t].re[i], fmaf(am[t].im[i], am[t].im[i], p));
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        if (q == 0) gpart[mc[t] * 16 * NS + 16 * mr[t] + m] = p;
+      }
     }
   }
 
-  // ---- back solve, row form Z L = Y^H
-  float2* zb = xb + (size_t)NB * 256;
-  for (int J = NB - 1; J >= 0; --J) {
-    __syncthreads();  // previous readers of the exchange blocks are done
+  // ---- back solve, row form Z L = Y^H (M holds Y^H on entry, Z on exit)
+  auto back_solve = [&]() {
+    float2* zb = xb + (size_t)NB * 256;
+    for (int J = NB - 1; J >= 0; --J) {
+      __syncthreads();  // previous readers of the exchange blocks are done
 #pragma unroll
-    for (int t = 0; t < NSLOT; ++t)  // L_JI^T (Linv_JJ^T at I = J)
-      if (kind[t] == 1 && row[t] == J) frag_store_t(xb + col[t] * 256, to_frag(acc[t]));
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < NSLOT; ++t) {
-      if (kind[t] == 2 && col[t] == J) {
-        const Frag P = to_frag(acc[t]);
-        Acc x = acc_zero();
-        mma_pq<false>(x, P, frag_load(xb + J * 256));
-        acc[t] = x;
-        frag_store(zb + row[t] * 256, to_frag(x));
-      }
-    }
-    if (J > 0) {
+      for (int t = 0; t < NSL; ++t)  // L_JI^T (Linv_JJ^T at I = J)
+        if (lv[t] && lr[t] == J) frag_store_t(xb + lc[t] * 256, to_frag(al[t]));
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NSLOT; ++t)
-        if (kind[t] == 2 && col[t] < J)
-          mma_pq<true>(acc[t], frag_load(zb + row[t] * 256), frag_load(xb + col[t] * 256));
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t] && mc[t] == J) {
+          const Frag P = to_frag(am[t]);
+          Acc x = acc_zero();
+          mma_pq<false>(x, P, frag_load(xb + J * 256));
+          am[t] = x;
+          frag_store(zb + mr[t] * 256, to_frag(x));
+        }
+      }
+      if (J > 0) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NSM; ++t)
+          if (mv[t] && mc[t] < J) mma_pq<true>(am[t], frag_load(zb + mr[t] * 256), frag_load(xb + mc[t] * 256));
+      }
+    }
+  };
+  back_solve();
+
+  if (REFINE) {
+    for (int it = 0; it < d.refine; ++it) {
+      // keep the current u = conj(Z) in W (this lane's own elements; read
+      // back by the same lane after the correction)
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t]) {
+          const int s = 16 * mr[t] + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * mc[t] + 4 * q + i;
+            if (s < S && k < D) W[s * D + k] = make_float2(am[t].re[i], -am[t].im[i]);
+          }
+        }
+      }
+      // residual in row form: conj(r) = conj(v) - Z R_L, FP64 MFMA (FP32
+      // operands converted exactly).  Every Z block is published; each M
+      // block's owner sums over J with one FP64 accumulator pair, whose lane
+      // (m, q) register i holds column q + 4i of the block.
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NSM; ++t)
+        if (mv[t]) frag_store(xb + (mr[t] * NB + mc[t]) * 256, to_frag(am[t]));
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t]) {
+          doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+          const float2* zrow = xb + (size_t)mr[t] * NB * 256 + 4 * lane;
+          const int c = 16 * mc[t] + m;
+          for (int J = 0; J < NB; ++J) {
+#pragma unroll 1
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const float2 z = zrow[J * 256 + s4];  // Z_{N,J}[m][4q + s4]
+              const int r = 16 * J + 4 * q + s4;    // R[r][c], c = 16 I + m
+              float2 rv;
+              if (r < D && c < D) {
+                rv = c <= r ? src.lower(r, c) : src.lower(c, r);
+                rv.y = c <= r ? rv.y : -rv.y;
+              } else {
+                rv = make_float2(r == c ? 1.f : 0.f, 0.f);
+              }
+              const double qr = rv.x, qi = rv.y, pr = z.x, pi = z.y;
+              cr = mfma64(qr, pr, cr);
+              cr = mfma64(-qi, pi, cr);
+              ci = mfma64(qr, pi, ci);
+              ci = mfma64(qi, pr, ci);
+            }
+          }
+          const int s = 16 * mr[t] + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * mc[t] + q + 4 * i;
+            const float2 v = (s < S && k < D) ? reload(steer + s * D + k) : make_float2(0.f, 0.f);
+            // the slot's Z is in LDS now: its registers hold the residual,
+            // column q + 4i in register i
+            am[t].re[i] = (float)((double)v.x - cr[i]);
+            am[t].im[i] = (float)(-(double)v.y - ci[i]);
+          }
+        }
+      }
+      __syncthreads();  // every Z block has been read
+      // conj(r) rounded to FP32, back into fragment order through the
+      // block's own (now free) Z position
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t]) {
+          float2* tb = xb + (mr[t] * NB + mc[t]) * 256;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) tb[bofs(m, q + 4 * i)] = make_float2(am[t].re[i], am[t].im[i]);
+          am[t] = to_acc(frag_load(tb));
+        }
+      }
+      // forward solve Y^H L^H = r^H with the stored factor
+      for (int J = 0; J < NB; ++J) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NSL; ++t)  // column J of L (Linv_JJ at the diagonal)
+          if (lv[t] && lc[t] == J) frag_store(xb + lr[t] * 256, to_frag(al[t]));
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NSM; ++t) {
+          if (mv[t] && mc[t] == J) {
+            const Frag P = to_frag(am[t]);
+            Acc x = acc_zero();
+            mma_pqh<false>(x, P, frag_load(xb + J * 256));
+            am[t] = x;
+            frag_store(xb + (NB + mr[t]) * 256, to_frag(x));
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NSM; ++t)
+          if (mv[t] && mc[t] > J)
+            mma_pqh<true>(am[t], frag_load(xb + (NB + mr[t]) * 256), frag_load(xb + mc[t] * 256));
+      }
+      back_solve();
+      // Z += the correction (u kept in W)
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t]) {
+          const int s = 16 * mr[t] + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * mc[t] + 4 * q + i;
+            if (s < S && k < D) {
+              const float2 u = reload(W + s * D + k);
+              am[t].re[i] += u.x;
+              am[t].im[i] -= u.y;
+            }
+          }
+        }
+      }
+    }
+    if (d.refine > 0) {
+      // gamma_s = Re(v_s^H u_s) in FP64 for the refined u, u = conj(Z)
+#pragma unroll
+      for (int t = 0; t < NSM; ++t) {
+        if (mv[t]) {
+          const int s = 16 * mr[t] + m;
+          double p = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * mc[t] + 4 * q + i;
+            if (s < S && k < D) {
+              const float2 v = reload(steer + s * D + k);
+              p += (double)v.x * am[t].re[i] - (double)v.y * am[t].im[i];  // Re(conj(v) conj(z))
+            }
+          }
+          p += __shfl_xor(p, 16);
+          p += __shfl_xor(p, 32);
+          if (q == 0) gpart[mc[t] * 16 * NS + 16 * mr[t] + m] = p;
+        }
+      }
     }
   }
   __syncthreads();  // gamma partials
 
   // ---- w_s = u_s / sqrt(gamma_s), u_s = conj(z_s)
 #pragma unroll
-  for (int t = 0; t < NSLOT; ++t) {
-    if (kind[t] == 2) {
-      const int s = 16 * row[t] + m;
-      float gam = 0.f;
+  for (int t = 0; t < NSM; ++t) {
+    if (mv[t]) {
+      const int s = 16 * mr[t] + m;
+      double gam = 0.0;
       for (int J = 0; J < NB; ++J) gam += gpart[J * 16 * NS + s];
-      const float sc = 1.f / sqrtf(gam);
+      const float sc = 1.f / sqrtf((float)gam);
       if (s < S) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = 16 * col[t] + 4 * q + i;
-          if (k < D) W[s * D + k] = make_float2(acc[t].re[i] * sc, -acc[t].im[i] * sc);
+          const int k = 16 * mc[t] + 4 * q + i;
+          if (k < D) W[s * D + k] = make_float2(am[t].re[i] * sc, -am[t].im[i] * sc);
         }
       }
     }

@@ -10,12 +10,11 @@ hipError_t launch_bfused_f32(const Dims& d, const float2* snap, const float2* st
 hipError_t launch_bfused_bf16(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
                               hipStream_t st, int waves);
 hipError_t launch_bfused_batched_f32(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer,
-                                     int waves, hipStream_t st);
+                                     int refine, int waves, hipStream_t st);
 hipError_t launch_bfused_batched_bf16(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer,
-                                      int waves, hipStream_t st);
+                                      int refine, int waves, hipStream_t st);
 
-// The blocked matrix-core solve runs without refinement.
-bool bfused_supported(const Dims& d) { return fused_supported(d) && d.refine == 0; }
+bool bfused_supported(const Dims& d) { return fused_supported(d); }
 
 hipError_t launch_fused(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
                         hipStream_t st, int ty) {
@@ -35,9 +34,9 @@ hipError_t launch_fused_batched32(const ProbDesc* desc, int n, long long total, 
 hipError_t launch_fused_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,
                                 int prec, int refine, int ty, hipStream_t st) {
   if (max_dof > 128 || prec == STAP_PREC_FP8 || total_sys <= 0) return hipErrorInvalidValue;
-  if ((ty == 4 || ty == 8) && refine == 0)
-    return prec == STAP_PREC_FP32 ? launch_bfused_batched_f32(desc, n, total_sys, max_dof, max_steer, ty, st)
-                                  : launch_bfused_batched_bf16(desc, n, total_sys, max_dof, max_steer, ty, st);
+  if (ty == 4 || ty == 8)
+    return prec == STAP_PREC_FP32 ? launch_bfused_batched_f32(desc, n, total_sys, max_dof, max_steer, refine, ty, st)
+                                  : launch_bfused_batched_bf16(desc, n, total_sys, max_dof, max_steer, refine, ty, st);
   if (ty == 32 && max_dof > 32) return launch_fused_batched32(desc, n, total_sys, max_dof, max_steer, prec, refine, st);
   return launch_fused_batched16(desc, n, total_sys, max_dof, max_steer, prec, refine, st);
 }

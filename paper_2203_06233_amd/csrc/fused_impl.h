@@ -83,18 +83,20 @@ __global__ __launch_bounds__(16 * TY) void fused_batched_kernel(const ProbDesc* 
 }
 
 // The same with the blocked matrix-core solve (bsolve_impl.h): NB block
-// columns of the covariance (compile time, for the covariance tiles), NW
-// waves, NSLOT register blocks per wave (enough for NB and the largest S).
-template <int NB, int NSLOT, int NW, int MODE>
+// columns of the covariance (compile time, for the covariance tiles), NS
+// steering blocks at most, NW waves, NSL / NSM register blocks per wave.  With REFINE the packed R_L stays in LDS for the FP64 residual and the
+// solver's exchange blocks follow it; without, they reuse the same bytes.
+template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
 __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, const float2* __restrict__ steer,
                                               float2* __restrict__ wout, int* __restrict__ info_out,
                                               const Dims& d, int sys) {
   using C = CovCfg<16 * NB, NW, MODE>;
-  using B = BCfg<NSLOT, NW>;
-  constexpr int PACK = 16 * NB * (16 * NB + 1) / 2 * 8;
-  constexpr int EXCH = (int)B::lds_bytes(NB, 4);
+  using B = BCfg<NSL, NSM, NW>;
+  constexpr int PACK = (16 * NB * (16 * NB + 1) / 2 * 8 + 255) / 256 * 256;
+  constexpr int EXCH = (int)B::lds_bytes(NB, NS);
   constexpr int B1 = C::LDS_BYTES > PACK ? C::LDS_BYTES : PACK;
-  constexpr int BYTES = B1 > EXCH ? B1 : EXCH;
+  constexpr int B2 = REFINE ? PACK + EXCH : EXCH;
+  constexpr int BYTES = B1 > B2 ? B1 : B2;
   __shared__ __align__(16) unsigned char lds[BYTES];
   __shared__ double dsum[16 * NB];
   __shared__ float red[NW];
@@ -110,20 +112,27 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
   float2* Rp = reinterpret_cast<float2*>(lds);
   cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
   __syncthreads();
-  bsolve_system<B>(PackedR{Rp}, steer, wout + (long long)sys * d.S * D, info_out ? info_out + sys : nullptr, d,
-                   lds);
+  bsolve_system<B, REFINE>(PackedR{Rp}, steer, wout + (long long)sys * d.S * D, info_out ? info_out + sys : nullptr,
+                           d, lds + (REFINE ? PACK : 0));
 }
 
-template <int NB, int NSLOT, int NW, int MODE>
-__global__ __launch_bounds__(64 * NW) void bfused_kernel(const float2* __restrict__ snap,
+// With refinement and 8 waves the register allocation is capped at 128 so
+// that two systems share a compute unit (a few registers spill).
+template <int NW, bool REFINE>
+constexpr int bfused_min_waves() { return REFINE && NW == 8 ? 4 : 1; }
+
+template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NW, REFINE>())))
+void bfused_kernel(const float2* __restrict__ snap,
                                                          const float2* __restrict__ steer,
                                                          float2* __restrict__ wout, int* __restrict__ info_out,
                                                          Dims d) {
-  bfused_system<NB, NSLOT, NW, MODE>(snap, steer, wout, info_out, d, blockIdx.x);
+  bfused_system<NB, NS, NSL, NSM, NW, MODE, REFINE>(snap, steer, wout, info_out, d, blockIdx.x);
 }
 
-template <int NB, int NSLOT, int NW, int MODE>
-__global__ __launch_bounds__(64 * NW) void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
+template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NW, REFINE>())))
+void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
                                                                  long long total) {
   for (long long g = blockIdx.x; g < total; g += gridDim.x) {
     int lo = 0, hi = n - 1;
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(64 * NW) void bfused_batched_kernel(const ProbDesc*
     }
     const ProbDesc& pd = desc[lo];
     const Dims d = pd.d;
-    bfused_system<NB, NSLOT, NW, MODE>(pd.snap, pd.steer, pd.w, pd.info, d, (int)(g - pd.sys_begin));
+    bfused_system<NB, NS, NSL, NSM, NW, MODE, REFINE>(pd.snap, pd.steer, pd.w, pd.info, d, (int)(g - pd.sys_begin));
     __syncthreads();
   }
 }

@@ -52,10 +52,7 @@ hipError_t launch_covariance(const Dims& d, const float2* snap, float2* cov, flo
 hipError_t launch_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                         hipStream_t st);
 
-// Blocked matrix-core solve (D <= 128, no refinement) with 4 or 8 waves per
-// system; bsolve_slots() is the register-block count it would use (0 = the
-// shape does not fit).
-int bsolve_slots(int D, int S, int waves);
+// Blocked matrix-core solve (D <= 128) with 4 or 8 waves per system.
 bool bsolve_supported(const Dims& d, int waves);
 hipError_t launch_bsolve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                          hipStream_t st, int waves);

@@ -24,9 +24,8 @@ CANDIDATES = (16, 32, 4, 8)
 
 
 def candidates(dof, refine):
-    """Variants worth timing for a shape: the 32-row grid needs D > 32, the
-    blocked solve runs without refinement."""
-    return [v for v in CANDIDATES if not (v == 32 and dof <= 32) and not (v in (4, 8) and refine > 0)]
+    """Variants worth timing for a shape (the 32-row grid needs D > 32)."""
+    return [v for v in CANDIDATES if not (v == 32 and dof <= 32)]
 
 
 def arch() -> str:

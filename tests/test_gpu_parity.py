@@ -169,13 +169,15 @@ def test_solve_parity(stap, shape, refine):
     _check_solve(stap, tiny_wl(shape), refine)
 
 
+@pytest.mark.parametrize("refine", [0, 1, 2])
 @pytest.mark.parametrize("waves", [4, 8])
 @pytest.mark.parametrize("shape", [s for s in SOLVE_SHAPES if s[0] * s[3] <= 128], ids=str)
-def test_blocked_solve_parity(stap, shape, waves):
-    """The blocked matrix-core solve, selected through the tuning table."""
+def test_blocked_solve_parity(stap, shape, waves, refine):
+    """The blocked matrix-core solve (with its FP64-MFMA refinement),
+    selected through the tuning table."""
     wl = tiny_wl(shape)
-    with solve_variant(stap, 1, wl.dof, wl.n_steer, "fp32", 0, waves):
-        _check_solve(stap, wl, 0, tag=f"bsolve{waves}")
+    with solve_variant(stap, 1, wl.dof, wl.n_steer, "fp32", refine, waves):
+        _check_solve(stap, wl, refine, tag=f"bsolve{waves}")
 
 
 def _check_solve(stap, wl, refine, tag="solve"):
@@ -397,20 +399,20 @@ def test_batched_run_equals_single(stap, precision, refine, graphs):
 
 
 @pytest.mark.parametrize("waves", [4, 8])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_batched_blocked_equals_single(stap, precision, waves):
+@pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 0), ("bf16", 1)])
+def test_batched_blocked_equals_single(stap, precision, refine, waves):
     """The persistent batched covariance -> blocked matrix-core solve gives
     each cube the single-cube blocked result (block products and reductions
     run in the same order whatever wave owns a block)."""
     wls = synth.uneven_batch(6)
     cubes = [dev(synth.make_cube(w)) for w in wls]
     Vs = [dev(synth.steering(w)) for w in wls]
-    probs = [prob_of(w, precision, 0) for w in wls]
+    probs = [prob_of(w, precision, refine) for w in wls]
     classes = [(d, s) for d in (16, 32, 48, 64, 96, 128) for s in (16, 32, 64)]
-    saved = {c: stap.tune_get(c[0], c[1], precision, 0) for c in classes}
+    saved = {c: stap.tune_get(c[0], c[1], precision, refine) for c in classes}
     try:
         for d, s in classes:
-            stap.tune_set(d, s, precision, 0, waves)
+            stap.tune_set(d, s, precision, refine, waves)
         Ws = [torch.empty((w.n_pulse, w.n_block, w.n_steer, w.dof), dtype=torch.complex64, device="cuda")
               for w in wls]
         batched = [host(p) for p in stap.Runner(probs).run(cubes, Vs, weights=Ws)]
@@ -421,11 +423,11 @@ def test_batched_blocked_equals_single(stap, precision, waves):
             assert metrics.rel_err(host(Ws[i]), host(W1)) <= 1e-6, i
         o = orc.run(synth.make_cube(wls[0]), synth.steering(wls[0]), wls[0].tdof, wls[0].n_block, wls[0].load_eps)
         we = metrics.rel_err(host(Ws[0]), o["W"])
-        _report("batched blocked", prec=precision, waves=waves, weights=we)
+        _report("batched blocked", prec=precision, refine=refine, waves=waves, weights=we)
         assert we <= 1e-3
     finally:
         for (d, s), v in saved.items():
-            stap.tune_set(d, s, precision, 0, v)
+            stap.tune_set(d, s, precision, refine, v)
 
 
 def test_graph_replays_equal_eager(stap):
@@ -479,16 +481,16 @@ def test_uneven_batch_64_sampled(stap):
 @pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 0), ("bf16", 1)])
 def test_fused_variants_match_oracle(stap, precision, refine):
     """Every solve variant of the fused covariance->solve kernel (the two
-    column-sweep thread grids and, without refinement, the blocked
-    matrix-core solve with 4 and 8 waves), selected through the tuning
-    table, against the oracle on the 48-DOF cube."""
+    column-sweep thread grids and the blocked matrix-core solve with 4 and 8
+    waves), selected through the tuning table, against the oracle on the
+    48-DOF cube."""
     wl = synth.MEDIUM
     cube = synth.make_cube(wl)
     V = synth.steering(wl)
     o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
     out = {}
     try:
-        for variant in (16, 32) + ((4, 8) if refine == 0 else ()):
+        for variant in (16, 32, 4, 8):
             stap.tune_set(wl.dof, wl.n_steer, precision, refine, variant)
             prob = prob_of(wl, precision, refine)
             W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
