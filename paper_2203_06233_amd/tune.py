@@ -92,13 +92,14 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
         e1.record(st)
         torch.cuda.synchronize()
         times[v] = e0.elapsed_time(e1) / reps
-        # every variant computes the same weights up to rounding order
+        # every variant computes the same weights up to rounding order (the
+        # systems are ill-conditioned, so only a gross disagreement is an error)
         w = W.cpu()
         if ref is None:
             ref = w
         else:
-            rel = float((w - ref).abs().max() / ref.abs().max())
-            if rel > 1e-3:
+            rel = float(torch.linalg.vector_norm(w - ref) / torch.linalg.vector_norm(ref))
+            if not rel <= 1e-2:
                 raise RuntimeError(f"variant {v} disagrees with the first variant timed: {rel}")
     best = min(times, key=times.get)
     stap.tune_set(wl.dof, wl.n_steer, precision, refine, best)
