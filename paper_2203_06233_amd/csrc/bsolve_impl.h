@@ -131,45 +131,49 @@ __device__ __forceinline__ float bcast(float v, int lane) {
 // Broadcast lane J of every 16-lane row to the whole row (DPP row_newbcast).
 template <int J>
 __device__ __forceinline__ float rowb(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, true));
 }
 template <int J>
 __device__ __forceinline__ float2 rowb2(float2 v) {
   return make_float2(rowb<J>(v.x), rowb<J>(v.y));
 }
 
-// Column j of the in-wave factorisation of diag_factor_inv().
+// Column j of the in-wave factorisation of diag_factor_inv().  Rows and
+// columns at or before j are never read again once column j is done, so the
+// update of A needs no mask: with l = A[m][j] / d_j^2 (unmasked) the lanes
+// take A[m][c] -= l A[j][c], which is right wherever m, c > j and harmless
+// elsewhere.  The inverse is kept with unscaled rows Y (X[m] = Y[m] / d_m):
+// rows below j take Y[m] -= (l_mj / d_j) Y[j]; the lane of row j records
+// 1 / d_j for the final scaling.
 template <int j>
-__device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, int q, int& fail) {
+__device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, float& rsm, int& fail) {
   constexpr int jq = j >> 2, ji = j & 3;
   const float piv = bcast(A.v[ji].x, j + 16 * jq);
   if (!(piv > 0.f)) {
     fail = j + 1;
     return;
   }
-  const float rs = __builtin_amdgcn_rsqf(piv);
+  const float rs = __builtin_amdgcn_rsqf(piv), r2 = rs * rs;
   const float2 amj = shfl2(A.v[ji], m + 16 * jq);  // A[m][j]
-  const float2 lm = (m > j) ? make_float2(amj.x * rs, amj.y * rs) : make_float2(0.f, 0.f);
+  const float2 la = make_float2(amj.x * r2, amj.y * r2);  // l_mj / d_j
+  const float2 lx = (m > j) ? la : make_float2(0.f, 0.f);
+  rsm = (m == j) ? rs : rsm;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int c = 4 * q + t;
     const float2 rj = rowb2<j>(A.v[t]);  // A[j][c] = conj(A[c][j])
-    const float2 xj = rowb2<j>(X.v[t]);  // X[j][c]
-    const float2 g = (c > j) ? make_float2(rj.x * rs, rj.y * rs) : make_float2(0.f, 0.f);  // conj(l_cj)
-    const float2 xs = make_float2(xj.x * rs, xj.y * rs);
-    // A[m][c] -= l_mj conj(l_cj);  X[m][c] -= l_mj X[j][c] / d_j
-    A.v[t].x = fmaf(-lm.x, g.x, fmaf(lm.y, g.y, A.v[t].x));
-    A.v[t].y = fmaf(-lm.x, g.y, fmaf(-lm.y, g.x, A.v[t].y));
-    X.v[t].x = fmaf(-lm.x, xs.x, fmaf(lm.y, xs.y, X.v[t].x));
-    X.v[t].y = fmaf(-lm.x, xs.y, fmaf(-lm.y, xs.x, X.v[t].y));
-    if (m == j) X.v[t] = xs;
+    const float2 yj = rowb2<j>(X.v[t]);  // Y[j][c]
+    // A[m][c] -= l_mj conj(l_cj) = (A[m][j] / d_j^2) A[j][c]
+    A.v[t].x = fmaf(-la.x, rj.x, fmaf(la.y, rj.y, A.v[t].x));
+    A.v[t].y = fmaf(-la.x, rj.y, fmaf(-la.y, rj.x, A.v[t].y));
+    X.v[t].x = fmaf(-lx.x, yj.x, fmaf(lx.y, yj.y, X.v[t].x));
+    X.v[t].y = fmaf(-lx.x, yj.y, fmaf(-lx.y, yj.x, X.v[t].y));
   }
 }
 template <int j>
-__device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, int q, int& fail) {
-  diag_col<j>(A, X, m, q, fail);
+__device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, float& rsm, int& fail) {
+  diag_col<j>(A, X, m, rsm, fail);
   if constexpr (j < 15) {
-    if (!fail) diag_cols<j + 1>(A, X, m, q, fail);
+    if (!fail) diag_cols<j + 1>(A, X, m, rsm, fail);
   }
 }
 
@@ -178,7 +182,7 @@ __device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, int q, int& f
 // d_j = sqrt(A[j][j]), l_mj = A[m][j] / d_j for m > j, then
 // A[m][c] -= l_mj conj(l_cj) for m, c > j; the inverse is accumulated as
 // X <- L_j^-1 X with L_j the identity carrying column j of L (row j of X
-// divided by d_j, then row m -= l_mj row j).  A[c][j] is read as conj(A[j][c])
+// divided by d_j, then row m -= l_mj row j), the row divisions deferred.  A[c][j] is read as conj(A[j][c])
 // from row j, which lives in the same 16-lane row of the wave (a DPP
 // broadcast); only l_mj crosses rows.  Returns 0 or the 1-based index of the
 // first non-positive pivot.
@@ -187,7 +191,10 @@ __device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
   int fail = 0;
-  diag_cols<0>(A, X, m, q, fail);
+  float rsm = 1.f;
+  diag_cols<0>(A, X, m, rsm, fail);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) X.v[i] = make_float2(X.v[i].x * rsm, X.v[i].y * rsm);
   return fail;
 }
 

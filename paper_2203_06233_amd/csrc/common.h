@@ -42,6 +42,15 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
+// Streaming stores for outputs that are written once and read back by a
+// later kernel (not by this one).
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v x = {v.x, v.y};
+  __builtin_nontemporal_store(x, reinterpret_cast<f2v*>(p));
+}
+__device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 

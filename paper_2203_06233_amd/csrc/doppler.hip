@@ -81,7 +81,7 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
       if (r3 < d.R) {
         float2* dst = snap + (long long)dof * d.R + r3;
 #pragma unroll
-        for (int k2 = 0; k2 < P2; ++k2) dst[(long long)(k1 + P1 * k2) * d.D * d.R] = z[k2];
+        for (int k2 = 0; k2 < P2; ++k2) store_stream(dst + (long long)(k1 + P1 * k2) * d.D * d.R, z[k2]);
       }
     }
     __syncthreads();

@@ -52,7 +52,8 @@ hipError_t launch_covariance(const Dims& d, const float2* snap, float2* cov, flo
 hipError_t launch_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                         hipStream_t st);
 
-// Blocked matrix-core solve (D <= 128) with 4 or 8 waves per system.
+// Blocked matrix-core solve with 4 or 8 waves per system (8 means 16 for
+// D > 128).
 bool bsolve_supported(const Dims& d, int waves);
 hipError_t launch_bsolve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                          hipStream_t st, int waves);

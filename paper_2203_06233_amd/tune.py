@@ -23,8 +23,12 @@ CACHE = os.environ.get("STAP_TUNE_CACHE",
 CANDIDATES = (16, 32, 4, 8)
 
 
-def candidates(dof, refine):
-    """Variants worth timing for a shape (the 32-row grid needs D > 32)."""
+def candidates(dof, refine, kind=0):
+    """Variants worth timing for a shape (the 32-row grid needs D > 32; above
+    D = 128 the column sweep picks its own grid and the blocked solve runs
+    with 16 waves under variant 8)."""
+    if dof > 128:
+        return [0, 8]
     return [v for v in CANDIDATES if not (v == 32 and dof <= 32)]
 
 
@@ -34,8 +38,18 @@ def arch() -> str:
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
-def key(arch_name, dof, n_steer, precision, refine):
-    return f"{arch_name}|fused|dof<={dof}|s<={n_steer}|{precision}|refine={int(refine > 0)}"
+KINDS = {"fused": 0, "stage": 1}
+
+
+def kind_of(wl, precision):
+    """stap_run takes the fused covariance->solve kernel (kind 0) for D <= 128
+    in FP32 or BF16, else the stage covariance and solve (kind 1)."""
+    return 0 if wl.dof <= 128 and precision != "fp8" else 1
+
+
+def key(arch_name, dof, n_steer, precision, refine, kind=0):
+    name = [k for k, v in KINDS.items() if v == kind][0]
+    return f"{arch_name}|{name}|dof<={dof}|s<={n_steer}|{precision}|refine={int(refine > 0)}"
 
 
 def load_cache(path=CACHE):
@@ -55,11 +69,12 @@ def apply_cache(stap, path=CACHE, arch_name=None):
         parts = k.split("|")
         if arch_name is not None and parts[0] != arch_name:
             continue
+        kind = KINDS[parts[1]]
         dof = int(parts[2].split("<=")[1])
         s = int(parts[3].split("<=")[1])
         prec = parts[4]
         refine = int(parts[5].split("=")[1])
-        stap.tune_set(dof, s, prec, refine, int(v["variant"]))
+        stap.tune_set(dof, s, prec, refine, int(v["variant"]), kind=kind)
         n += 1
     return n
 
@@ -80,8 +95,9 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
     W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device=dev)
     times = {}
     ref = None
-    for v in candidates(wl.dof, refine):
-        stap.tune_set(wl.dof, wl.n_steer, precision, refine, v)
+    kind = kind_of(wl, precision)
+    for v in candidates(wl.dof, refine, kind):
+        stap.tune_set(wl.dof, wl.n_steer, precision, refine, v, kind=kind)
         for _ in range(warmup):
             runner.run([cube], [V], powers=[power], weights=[W])
         st = torch.cuda.current_stream()
@@ -102,13 +118,13 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
             if not rel <= 1e-2:
                 raise RuntimeError(f"variant {v} disagrees with the first variant timed: {rel}")
     best = min(times, key=times.get)
-    stap.tune_set(wl.dof, wl.n_steer, precision, refine, best)
+    stap.tune_set(wl.dof, wl.n_steer, precision, refine, best, kind=kind)
     return best, times
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="all", choices=["all", "small", "medium", "large", "uneven"])
+    ap.add_argument("--workload", default="all", choices=["all", "small", "medium", "large", "xlarge", "uneven"])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=CACHE)
     args = ap.parse_args()
@@ -116,7 +132,7 @@ def main():
     sys.path.insert(0, root)
     import synth
 
-    sel = {"small": [synth.SMALL], "medium": [synth.MEDIUM], "large": [synth.LARGE],
+    sel = {"small": [synth.SMALL], "medium": [synth.MEDIUM], "large": [synth.LARGE], "xlarge": [synth.XLARGE],
            "uneven": synth.uneven_batch(8)}
     wls = sum(sel.values(), []) if args.workload == "all" else sel[args.workload]
     a = arch()
@@ -127,8 +143,9 @@ def main():
     for wl in wls:
         dc = next(c for c in dof_cls if wl.dof <= c)
         sc = next(c for c in s_cls if wl.n_steer <= c)
-        for precision, refine in (("fp32", 0), ("bf16", 1), ("bf16", 0)):
-            k = key(a, dc, sc, precision, refine)
+        combos = (("fp32", 0), ("fp8", 1)) if wl.dof > 128 else (("fp32", 0), ("bf16", 1), ("bf16", 0))
+        for precision, refine in combos:
+            k = key(a, dc, sc, precision, refine, kind_of(wl, precision))
             if k in seen:
                 continue
             seen.add(k)

@@ -171,10 +171,10 @@ def test_solve_parity(stap, shape, refine):
 
 @pytest.mark.parametrize("refine", [0, 1, 2])
 @pytest.mark.parametrize("waves", [4, 8])
-@pytest.mark.parametrize("shape", [s for s in SOLVE_SHAPES if s[0] * s[3] <= 128], ids=str)
+@pytest.mark.parametrize("shape", SOLVE_SHAPES, ids=str)
 def test_blocked_solve_parity(stap, shape, waves, refine):
     """The blocked matrix-core solve (with its FP64-MFMA refinement),
-    selected through the tuning table."""
+    selected through the tuning table (8 waves run D > 128 on 16)."""
     wl = tiny_wl(shape)
     with solve_variant(stap, 1, wl.dof, wl.n_steer, "fp32", refine, waves):
         _check_solve(stap, wl, refine, tag=f"bsolve{waves}")
@@ -358,17 +358,23 @@ def test_chain_large_sampled(stap, precision, refine):
             assert pe <= 1e-4
 
 
-def test_stages_equal_run_and_deterministic(stap):
+@pytest.mark.parametrize("variant", [16, 8])
+def test_stages_equal_run_and_deterministic(stap, variant):
+    """The stage calls and stap_run (fused covariance->solve) give bitwise the
+    same power when both use the same solve variant, and runs repeat
+    bitwise."""
     wl = synth.SMALL
     cube = dev(synth.make_cube(wl))
     V = dev(synth.steering(wl))
     prob = prob_of(wl, "bf16", 1)
-    X = stap.doppler(prob, cube)
-    cov, _ = stap.covariance(prob, X)
-    w, info = stap.solve_weights(prob, cov, V)
-    p_stage = host(stap.inner_products(prob, w, X))
-    p1 = host(stap.run([prob], [cube], [V])[0])
-    p2 = host(stap.run([prob], [cube], [V])[0])
+    with solve_variant(stap, 0, wl.dof, wl.n_steer, "bf16", 1, variant), \
+            solve_variant(stap, 1, wl.dof, wl.n_steer, "bf16", 1, variant):
+        X = stap.doppler(prob, cube)
+        cov, _ = stap.covariance(prob, X)
+        w, info = stap.solve_weights(prob, cov, V)
+        p_stage = host(stap.inner_products(prob, w, X))
+        p1 = host(stap.run([prob], [cube], [V])[0])
+        p2 = host(stap.run([prob], [cube], [V])[0])
     assert np.array_equal(p1, p2)
     assert np.array_equal(p_stage, p1)
 
@@ -377,11 +383,17 @@ def test_stages_equal_run_and_deterministic(stap):
 @pytest.mark.parametrize("precision,refine", [("fp32", 0), ("bf16", 1)])
 def test_batched_run_equals_single(stap, precision, refine, graphs):
     """The batched path (one launch per kernel over every cube, persistent
-    covariance->solve kernel) gives each cube the single-cube result."""
+    covariance->solve kernel) gives each cube the single-cube result, with
+    the column-sweep solve pinned for every shape class (the blocked solve
+    has its own test)."""
     wls = synth.uneven_batch(6)
     cubes = [dev(synth.make_cube(w)) for w in wls]
     Vs = [dev(synth.steering(w)) for w in wls]
     probs = [prob_of(w, precision, refine) for w in wls]
+    classes = [(d, s) for d in (16, 32, 48, 64, 96, 128) for s in (16, 32, 64)]
+    saved = {c: stap.tune_get(c[0], c[1], precision, refine) for c in classes}
+    for d, s in classes:
+        stap.tune_set(d, s, precision, refine, 16)
     stap.use_graphs(graphs)
     try:
         Ws = [torch.empty((w.n_pulse, w.n_block, w.n_steer, w.dof), dtype=torch.complex64, device="cuda")
@@ -396,6 +408,8 @@ def test_batched_run_equals_single(stap, precision, refine, graphs):
             assert metrics.rel_err(Wb[i], host(W1)) <= 1e-6, i
     finally:
         stap.use_graphs(True)
+        for (d, s), v in saved.items():
+            stap.tune_set(d, s, precision, refine, v)
 
 
 @pytest.mark.parametrize("waves", [4, 8])
@@ -505,6 +519,30 @@ def test_fused_variants_match_oracle(stap, precision, refine):
         assert we <= 1e-3
         assert pe <= 1e-4
     assert metrics.rel_err(out[32][1], out[16][1]) <= 1e-4
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+@pytest.mark.parametrize("variant", [4, 8])
+def test_fused_blocked_dof128(stap, variant, refine):
+    """The fused blocked kernels at the largest fused class (D = 128, three
+    steering blocks): refinement keeps the packed covariance and every Z
+    block in LDS next to each other."""
+    wl = tiny_wl((32, 32, 256, 4, 2, 40))
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+    with solve_variant(stap, 0, wl.dof, wl.n_steer, "bf16", refine, variant):
+        prob = prob_of(wl, "bf16", refine)
+        W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
+        info = torch.empty((wl.n_pulse, wl.n_block), dtype=torch.int32, device="cuda")
+        power = stap.run([prob], [dev(cube)], [dev(V)], weights=[W], info=[info])[0]
+    assert np.all(host(info) == 0)
+    we = metrics.rel_err(host(W), o["W"])
+    sl = metrics.sinr_loss_db(host(W), o["W"], V, o["R_L"])
+    _report("fused dof128", variant=variant, refine=refine, weights=we, sinr_max=float(sl.max()),
+            power=metrics.rel_err(host(power), o["power"]))
+    assert we <= 1e-3
+    assert sl.max() <= 0.1
 
 
 def test_chain_dof_above_128(stap):
