@@ -209,6 +209,13 @@ def main():
         plain = dict(ms_per_step=wall_p * 1e3, value=cells_dof / wall_p)
         del pw, ww, ii
         torch.cuda.empty_cache()
+    # the same precision without the refinement step, for context
+    unrefined = None
+    if not args.no_plain and args.refine > 0:
+        wall_u, ev_u, pw, ww, ii = time_run(args.precision, 0)
+        unrefined = dict(ms_per_step=wall_u * 1e3, value=cells_dof / wall_u)
+        del pw, ww, ii
+        torch.cuda.empty_cache()
 
     # per-kernel durations with HIP events on the launch stream (single cube)
     kern = {}
@@ -315,6 +322,7 @@ def main():
         "event_ms_per_step": ev_m,
         "plain_fp32": plain,
         "mixed_over_plain": (value / plain["value"]) if plain else None,
+        "mixed_without_refinement": unrefined,
         "accuracy": acc,
         "kernels": kern,
         "roofline": roof,
