@@ -24,9 +24,9 @@
 // X[m][4q + i], i = 0..3.  This is the MFMA result layout of X^T, and the A
 // and B operand layouts of a product whose k index runs over the block
 // columns, so every product is formed transposed (X^T -= conj(Q) P^T) and no
-// block is ever shuffled.  In LDS a block keeps the same order (lane-major,
-// 32 bytes per lane), so a fragment load is two 16-byte reads per lane with
-// consecutive lanes on consecutive addresses.
+// block is ever shuffled.  In LDS a block keeps the same order (registers
+// 0-1 of all lanes, then registers 2-3), so a fragment load is two 16-byte
+// reads per lane with consecutive lanes on consecutive addresses.
 #pragma once
 
 #include "common.h"
@@ -40,13 +40,20 @@ struct Acc {
   floatx4 re, im;
 };
 
-// Complex offset of element (r, c) of a block stored in fragment order.
-__device__ __forceinline__ int bofs(int r, int c) { return 4 * r + 64 * (c >> 2) + (c & 3); }
+// Complex offset of element (r, c) of a block stored in fragment order: the
+// lane holding it is l = r + 16 (c / 4), its register i = c % 4; registers
+// 0-1 of every lane come first (16 bytes per lane), then registers 2-3, so
+// each of the two 16-byte accesses of a fragment covers one contiguous
+// kilobyte across the wave.
+__device__ __forceinline__ int bofs(int r, int c) {
+  const int l = r + 16 * (c >> 2), i = c & 3;
+  return (i < 2 ? 0 : 128) + 2 * l + (i & 1);
+}
 
 __device__ __forceinline__ Frag frag_load(const float2* blk) {
   const int l = threadIdx.x & 63;
-  const float4* p = reinterpret_cast<const float4*>(blk + 4 * l);
-  const float4 a = p[0], b = p[1];
+  const float4 a = *reinterpret_cast<const float4*>(blk + 2 * l);
+  const float4 b = *reinterpret_cast<const float4*>(blk + 128 + 2 * l);
   Frag f;
   f.v[0] = make_float2(a.x, a.y);
   f.v[1] = make_float2(a.z, a.w);
@@ -56,9 +63,8 @@ __device__ __forceinline__ Frag frag_load(const float2* blk) {
 }
 __device__ __forceinline__ void frag_store(float2* blk, const Frag& f) {
   const int l = threadIdx.x & 63;
-  float4* p = reinterpret_cast<float4*>(blk + 4 * l);
-  p[0] = make_float4(f.v[0].x, f.v[0].y, f.v[1].x, f.v[1].y);
-  p[1] = make_float4(f.v[2].x, f.v[2].y, f.v[3].x, f.v[3].y);
+  *reinterpret_cast<float4*>(blk + 2 * l) = make_float4(f.v[0].x, f.v[0].y, f.v[1].x, f.v[1].y);
+  *reinterpret_cast<float4*>(blk + 128 + 2 * l) = make_float4(f.v[2].x, f.v[2].y, f.v[3].x, f.v[3].y);
 }
 // Store X^T: the lane's X[m][4q + i] goes to element (4q + i, m).
 __device__ __forceinline__ void frag_store_t(float2* blk, const Frag& f) {
@@ -485,12 +491,12 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
       for (int t = 0; t < NSM; ++t) {
         if (mv[t]) {
           doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
-          const float2* zrow = xb + (size_t)mr[t] * NB * 256 + 4 * lane;
+          const float2* zrow = xb + (size_t)mr[t] * NB * 256 + 2 * lane;
           const int c = 16 * mc[t] + m;
           for (int J = 0; J < NB; ++J) {
 #pragma unroll 1
             for (int s4 = 0; s4 < 4; ++s4) {
-              const float2 z = zrow[J * 256 + s4];  // Z_{N,J}[m][4q + s4]
+              const float2 z = zrow[J * 256 + (s4 & 2) * 64 + (s4 & 1)];  // Z_{N,J}[m][4q + s4]
               const int r = 16 * J + 4 * q + s4;    // R[r][c], c = 16 I + m
               float2 rv;
               if (r < D && c < D) {

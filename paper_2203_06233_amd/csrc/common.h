@@ -216,25 +216,24 @@ __device__ __forceinline__ void fft_inreg(float2 (&v)[M]) {
 }
 
 // Round-to-nearest-even float -> bf16 bits, and back.
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned int u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
-
 __device__ __forceinline__ uint4 negbf8(uint4 u) {
   return make_uint4(u.x ^ 0x80008000u, u.y ^ 0x80008000u, u.z ^ 0x80008000u, u.w ^ 0x80008000u);
 }
 
-// Split x into three bf16 terms with x = h + m + l to about 24 bits: each
-// residual is exact in FP32, so h*h' etc. are exact products in FP32.
-__device__ __forceinline__ void split3(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
-  h = f2bf(x);
-  float r1 = x - bf2f(h);
-  m = f2bf(r1);
-  float r2 = r1 - bf2f(m);
-  l = f2bf(r2);
+// Three-term BF16 split of two floats at once, packed in pairs (a in the low
+// half): x = h + m + l to 24 bits, each term rounded to nearest even by the
+// hardware pair conversion (v_cvt_pk_bf16_f32); each residual is exact in
+// FP32, so the products of terms are exact in FP32.
+__device__ __forceinline__ void split3x2(float a, float b, unsigned int& h, unsigned int& m, unsigned int& l) {
+  typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+  typedef float f32x2v __attribute__((ext_vector_type(2)));
+  const f32x2v x = {a, b};
+  const bf16x2v hb = __builtin_convertvector(x, bf16x2v);
+  h = __builtin_bit_cast(unsigned int, hb);
+  const f32x2v r1 = {a - __uint_as_float(h << 16), b - __uint_as_float(h & 0xFFFF0000u)};
+  const bf16x2v mb = __builtin_convertvector(r1, bf16x2v);
+  m = __builtin_bit_cast(unsigned int, mb);
+  const f32x2v r2 = {r1.x - __uint_as_float(m << 16), r1.y - __uint_as_float(m & 0xFFFF0000u)};
+  l = __builtin_bit_cast(unsigned int, __builtin_convertvector(r2, bf16x2v));
 }
-
 }  // namespace stap

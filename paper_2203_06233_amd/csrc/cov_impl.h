@@ -130,18 +130,16 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
           if (2 * cp < nc) v0 = src[0];
           if (2 * cp + 1 < nc) v1 = src[1];
         }
-        unsigned short h0, m0, l0, h1, m1, l1;
+        unsigned int h, m, l;
         const int base = row * (BF_PITCH / 2) + cp;
-        split3(v0.x, h0, m0, l0);
-        split3(v1.x, h1, m1, l1);
-        pl[0 * PS + base] = h0 | ((unsigned int)h1 << 16);
-        pl[1 * PS + base] = m0 | ((unsigned int)m1 << 16);
-        pl[2 * PS + base] = l0 | ((unsigned int)l1 << 16);
-        split3(v0.y, h0, m0, l0);
-        split3(v1.y, h1, m1, l1);
-        pl[3 * PS + base] = h0 | ((unsigned int)h1 << 16);
-        pl[4 * PS + base] = m0 | ((unsigned int)m1 << 16);
-        pl[5 * PS + base] = l0 | ((unsigned int)l1 << 16);
+        split3x2(v0.x, v1.x, h, m, l);
+        pl[0 * PS + base] = h;
+        pl[1 * PS + base] = m;
+        pl[2 * PS + base] = l;
+        split3x2(v0.y, v1.y, h, m, l);
+        pl[3 * PS + base] = h;
+        pl[4 * PS + base] = m;
+        pl[5 * PS + base] = l;
       }
     } else {
       unsigned char* pl = lds;

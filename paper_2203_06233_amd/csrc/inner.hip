@@ -118,9 +118,6 @@ __device__ __forceinline__ floatx4 mfma_bf16x(uint4 a, uint4 b, floatx4 c) {
                                                  c, 0, 0, 0);
 }
 
-__device__ __forceinline__ unsigned int pack2(unsigned short lo, unsigned short hi) {
-  return (unsigned int)lo | ((unsigned int)hi << 16);
-}
 
 // Split-BF16 variant.  LDS holds the weights as six planes
 // [re h, re m, re l, im h, im m, im l][s][d] (d padded to DP, pitch DP + 8).
@@ -143,18 +140,16 @@ __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts
       if (q < D) w0 = W[s * D + q];
       if (q + 1 < D) w1 = W[s * D + q + 1];
     }
-    unsigned short h0, m0, l0, h1, m1, l1;
+    unsigned int h, m, l;
     const int o = s * (PITCH / 2) + q / 2;
-    split3(w0.x, h0, m0, l0);
-    split3(w1.x, h1, m1, l1);
-    wp[0 * PS + o] = pack2(h0, h1);
-    wp[1 * PS + o] = pack2(m0, m1);
-    wp[2 * PS + o] = pack2(l0, l1);
-    split3(w0.y, h0, m0, l0);
-    split3(w1.y, h1, m1, l1);
-    wp[3 * PS + o] = pack2(h0, h1);
-    wp[4 * PS + o] = pack2(m0, m1);
-    wp[5 * PS + o] = pack2(l0, l1);
+    split3x2(w0.x, w1.x, h, m, l);
+    wp[0 * PS + o] = h;
+    wp[1 * PS + o] = m;
+    wp[2 * PS + o] = l;
+    split3x2(w0.y, w1.y, h, m, l);
+    wp[3 * PS + o] = h;
+    wp[4 * PS + o] = m;
+    wp[5 * PS + o] = l;
   }
   __syncthreads();
   const uint4* wp4 = reinterpret_cast<const uint4*>(wp);
@@ -182,17 +177,8 @@ __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts
         const int q = q0 + 8 * (lane >> 4) + j;
         const float2 x0 = (live && q < D) ? X[(long long)q * d.R + r] : make_float2(0.f, 0.f);
         const float2 x1 = (live && q + 1 < D) ? X[(long long)(q + 1) * d.R + r] : make_float2(0.f, 0.f);
-        unsigned short h0, m0, l0, h1, m1, l1;
-        split3(x0.x, h0, m0, l0);
-        split3(x1.x, h1, m1, l1);
-        xb[0][j / 2] = pack2(h0, h1);
-        xb[1][j / 2] = pack2(m0, m1);
-        xb[2][j / 2] = pack2(l0, l1);
-        split3(x0.y, h0, m0, l0);
-        split3(x1.y, h1, m1, l1);
-        xb[3][j / 2] = pack2(h0, h1);
-        xb[4][j / 2] = pack2(m0, m1);
-        xb[5][j / 2] = pack2(l0, l1);
+        split3x2(x0.x, x1.x, xb[0][j / 2], xb[1][j / 2], xb[2][j / 2]);
+        split3x2(x0.y, x1.y, xb[3][j / 2], xb[4][j / 2], xb[5][j / 2]);
       }
       uint4 Bv[6];
 #pragma unroll
