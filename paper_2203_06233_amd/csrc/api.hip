@@ -396,7 +396,7 @@ const char* stap_status_string(stap_status status) {
     case STAP_ERR_ALIGN: return "misaligned device pointer";
     case STAP_ERR_WORKSPACE: return "workspace missing or too small";
     case STAP_ERR_HIP: return "HIP runtime error";
-    case STAP_ERR_UNSUPPORTED: return "request not supported by this build";
+    case STAP_ERR_UNSUPPORTED: return "request not supported by the library";
   }
   return "unknown status";
 }
