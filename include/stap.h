@@ -182,8 +182,13 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs,
  *          16 or 32 = column-sweep solve with 16 or 32 rows per register
  *                     slot (a 16 x 16 or 32 x 16 thread grid per system);
  *          4 or 8   = blocked solve on the FP32 matrix cores with 4 or 8
- *                     waves per system (D <= 128 and refine_steps = 0; other
- *                     requests in the class take the default).
+ *                     waves per system (8 runs D > 128 on 16 waves);
+ *          1        = one wave per system with every block of the solve in
+ *                     its registers (D <= 96, S <= 32): the stage solve
+ *                     (kind 1), and for kind 0 a route of single-cube
+ *                     stap_run calls through the stage covariance and that
+ *                     solve (stap_covariance_solve then takes variant 8).
+ *          Requests a variant does not cover take the default. 
  * Not thread-safe with respect to concurrent stap_run calls.  Returns
  * STAP_ERR_ARG for values out of range. */
 stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t precision, int32_t refine,

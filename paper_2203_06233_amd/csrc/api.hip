@@ -79,7 +79,7 @@ constexpr int kDofClass[] = {16, 32, 48, 64, 96, 128, 160, 192};
 constexpr int kSteerClass[] = {16, 32, 64};
 constexpr int kKinds = 2;
 int8_t g_tune[kKinds][8][3][3][2];
-bool valid_variant(int v) { return v == 0 || v == 4 || v == 8 || v == 16 || v == 32; }
+bool valid_variant(int v) { return v == 0 || v == 1 || v == 4 || v == 8 || v == 16 || v == 32; }
 
 int dof_class(int d) {
   for (int i = 0; i < 8; ++i)
@@ -96,15 +96,24 @@ int tuned(int kind, const Dims& d) {
   if (dc < 0 || sc < 0) return 0;
   return g_tune[kind][dc][sc][d.prec][d.refine > 0 ? 1 : 0];
 }
+// Variant of the fused covariance -> solve kernel; variant 1 of kind 0 is
+// not a fused kernel but stap_run's stage route (one_wave_route()), so the
+// fused entry point takes the blocked 8-wave kernel for it.
 int fused_variant(const Dims& d) {
   const int v = tuned(0, d);
-  return v == 0 ? 16 : v;
+  return v == 0 ? 16 : v == 1 ? 8 : v;
 }
-// Stage solve: the blocked matrix-core solve (variant 4 or 8 waves) where
-// the table asks for it and the shape allows, else the column-sweep solve.
+// stap_run on one cube: the stage covariance and the one-wave solve instead
+// of the fused kernel, where the table asks for it (kind 0, variant 1) and
+// the shape allows.
+bool one_wave_route(const Dims& d) { return tuned(0, d) == 1 && stap::wsolve_supported(d); }
+// Stage solve: the one-wave register-resident solve (variant 1) or the
+// blocked matrix-core solve (variant 4 or 8 waves) where the table asks for
+// it and the shape allows, else the column-sweep solve.
 hipError_t stage_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                        hipStream_t st) {
   const int v = tuned(1, d);
+  if (v == 1 && stap::wsolve_supported(d)) return stap::launch_wsolve(d, cov, steer, w, info, st);
   if ((v == 4 || v == 8) && stap::bsolve_supported(d, v)) return stap::launch_bsolve(d, cov, steer, w, info, st, v);
   return stap::launch_solve(d, cov, steer, w, info, st);
 }
@@ -113,8 +122,8 @@ constexpr size_t kAlign = 256;
 size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace of one cube: snapshots, weights and info (when the caller passes
-// none), and the covariance and delta only where the fused kernel does not
-// apply (D > 128 or FP8).
+// none), and the covariance and delta where the fused kernel does not apply
+// (D > 128 or FP8) or the one-wave stage route may (D <= 96, S <= 32).
 struct Parts {
   size_t snap, cov, delta, w, info;
   size_t total() const { return snap + cov + delta + w + info; }
@@ -122,7 +131,8 @@ struct Parts {
 Parts parts_of(const stap_problem* q) {
   const size_t P = q->n_pulse, D = (size_t)q->tdof * q->n_chan, R = q->n_range, B = q->n_block,
                S = q->n_steer;
-  const bool fused = stap::fused_supported(dims_of(q));
+  const Dims d = dims_of(q);
+  const bool fused = stap::fused_supported(d) && !stap::wsolve_supported(d);
   Parts p;
   p.snap = up(P * D * R * 8);
   p.cov = fused ? 0 : up(P * B * D * D * 8);
@@ -280,7 +290,10 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
       float* delta = reinterpret_cast<float*>(wsp + p.snap + p.cov);
       wsp += p.total();
       hipError_t e = stap::launch_doppler(d, pd.cube, pd.snap, st);
-      if (stap::fused_supported(d)) {
+      if (one_wave_route(d)) {
+        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);
+        if (e == hipSuccess) e = stap::launch_wsolve(d, cov, pd.steer, pd.w, pd.info, st);
+      } else if (stap::fused_supported(d)) {
         if (e == hipSuccess) e = stap::launch_fused(d, pd.snap, pd.steer, pd.w, pd.info, st, fused_variant(d));
       } else {
         if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);

@@ -14,8 +14,11 @@ struct GlobalRB {
   __device__ float2 lower(int i, int k) const { return A[(long long)i * D + k]; }
 };
 
+// With refinement and 8 waves the register allocation is capped at 128 so
+// that two systems share a compute unit.
 template <int NSL, int NSM, int NW, bool REFINE>
-__global__ __launch_bounds__(64 * NW) void bsolve_kernel(const float2* __restrict__ cov,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(REFINE && NW == 8 ? 4 : 1)))
+void bsolve_kernel(const float2* __restrict__ cov,
                                                          const float2* __restrict__ steer,
                                                          float2* __restrict__ wout, int* __restrict__ info_out,
                                                          Dims d) {

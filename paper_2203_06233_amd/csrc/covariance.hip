@@ -34,10 +34,36 @@ __global__ __launch_bounds__(NW * 64) void cov_kernel(const float2* __restrict__
   const float dl = cov_delta<Cfg>(accR, D, d.eps, dsum, &s_delta);
   if (delta_out && threadIdx.x == 0) delta_out[sys] = dl;
   float2* out = cov + (long long)sys * D * D;
+  // lower triangle: for each register the 16 lanes of a row write 16
+  // consecutive elements of one matrix row
   cov_emit<Cfg>(accR, accI, D, dl, [&](int row, int col, float2 v) {
     out[(long long)row * D + col] = v;
-    if (row != col) out[(long long)col * D + row] = make_float2(v.x, -v.y);
   });
+  // upper triangle as the conjugate transpose: the lane's four registers
+  // are four consecutive elements of one matrix row of the upper part, so
+  // off-diagonal tiles inside D go out as two 16-byte stores per lane
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool vec_ok = (reinterpret_cast<uintptr_t>(out) & 15) == 0;  // the ABI asks for 8-byte alignment only
+#pragma unroll
+  for (int i = 0; i < Cfg::TPW; ++i) {
+    const int t = wave + NW * i;
+    if (t < Cfg::NTILE) {
+      int I, J;
+      cov_tile_of(t, I, J);
+      const int col = J * 16 + (lane & 15), row0 = I * 16 + 4 * (lane >> 4);
+      if (I > J && 16 * I + 16 <= D && (D & 1) == 0 && vec_ok) {
+        float4* dst = reinterpret_cast<float4*>(out + (long long)col * D + row0);
+        dst[0] = make_float4(accR[i][0], -accI[i][0], accR[i][1], -accI[i][1]);
+        dst[1] = make_float4(accR[i][2], -accI[i][2], accR[i][3], -accI[i][3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + r;
+          if (row < D && col < D && row > col) out[(long long)col * D + row] = make_float2(accR[i][r], -accI[i][r]);
+        }
+      }
+    }
+  }
 }
 
 template <int DP, int NW>

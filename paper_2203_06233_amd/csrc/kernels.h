@@ -55,6 +55,10 @@ hipError_t launch_solve(const Dims& d, const float2* cov, const float2* steer, f
 // Blocked matrix-core solve with 4 or 8 waves per system (8 means 16 for
 // D > 128).
 bool bsolve_supported(const Dims& d, int waves);
+// one wave per system, every block in registers (D <= 96, S <= 32)
+bool wsolve_supported(const Dims& d);
+hipError_t launch_wsolve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
+                         hipStream_t st);
 hipError_t launch_bsolve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
                          hipStream_t st, int waves);
 

@@ -1,0 +1,11 @@
+// One-wave stage solve, steering class 2 (S <= 32), refinement off.
+#include "wsolve_launch.h"
+
+namespace stap {
+
+hipError_t launch_wsolve_r0_s2(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
+                                  hipStream_t st) {
+  return wsv::by_nb<2, false>(d, cov, steer, w, info, st);
+}
+
+}  // namespace stap

@@ -2,9 +2,9 @@
 
 For each shape class it runs stap_run on a seeded cube of that shape under
 every candidate variant of the fused covariance->solve kernel (the
-column-sweep solve on a 16 x 16 or 32 x 16 thread grid per system, or the
-blocked matrix-core solve with 4 or 8 waves), keeps the fastest by HIP-event
-time, and
+column-sweep solve on a 16 x 16 or 32 x 16 thread grid per system, the
+blocked matrix-core solve with 4 or 8 waves, or the stage covariance
+followed by the one-wave solve), keeps the fastest by HIP-event time, and
 stores the choice in a JSON cache keyed by GPU architecture, DOF class,
 steering class, precision and refinement.  The binding applies the cache
 (``tune_cache.json`` beside this file, or ``$STAP_TUNE_CACHE``) at import.
@@ -23,13 +23,18 @@ CACHE = os.environ.get("STAP_TUNE_CACHE",
 CANDIDATES = (16, 32, 4, 8)
 
 
-def candidates(dof, refine, kind=0):
+def candidates(dof, refine, kind=0, n_steer=16):
     """Variants worth timing for a shape (the 32-row grid needs D > 32; above
     D = 128 the column sweep picks its own grid and the blocked solve runs
-    with 16 waves under variant 8)."""
+    with 16 waves under variant 8).  Variant 1 (D <= 96, S <= 32) is the
+    one-wave register-resident solve: as a stage solve (kind 1), and for
+    kind 0 stap_run's route through the stage covariance and that solve."""
     if dof > 128:
         return [0, 8]
-    return [v for v in CANDIDATES if not (v == 32 and dof <= 32)]
+    out = [v for v in CANDIDATES if not (v == 32 and dof <= 32)]
+    if dof <= 96 and n_steer <= 32:
+        out.append(1)
+    return out
 
 
 def arch() -> str:
@@ -96,7 +101,7 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
     times = {}
     ref = None
     kind = kind_of(wl, precision)
-    for v in candidates(wl.dof, refine, kind):
+    for v in candidates(wl.dof, refine, kind, wl.n_steer):
         stap.tune_set(wl.dof, wl.n_steer, precision, refine, v, kind=kind)
         for _ in range(warmup):
             runner.run([cube], [V], powers=[power], weights=[W])

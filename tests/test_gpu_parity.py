@@ -170,11 +170,13 @@ def test_solve_parity(stap, shape, refine):
 
 
 @pytest.mark.parametrize("refine", [0, 1, 2])
-@pytest.mark.parametrize("waves", [4, 8])
+@pytest.mark.parametrize("waves", [1, 4, 8])
 @pytest.mark.parametrize("shape", SOLVE_SHAPES, ids=str)
 def test_blocked_solve_parity(stap, shape, waves, refine):
-    """The blocked matrix-core solve (with its FP64-MFMA refinement),
-    selected through the tuning table (8 waves run D > 128 on 16)."""
+    """The blocked matrix-core solves (with their FP64-MFMA refinement),
+    selected through the tuning table: one wave per system with every block
+    in registers (D <= 96, S <= 32; other shapes fall back to the column
+    sweep), or 4 / 8 waves (8 run D > 128 on 16)."""
     wl = tiny_wl(shape)
     with solve_variant(stap, 1, wl.dof, wl.n_steer, "fp32", refine, waves):
         _check_solve(stap, wl, refine, tag=f"bsolve{waves}")
@@ -214,7 +216,7 @@ def test_refinement_reduces_solve_error(stap):
     assert errs[2] <= errs[1] + 2e-7
 
 
-@pytest.mark.parametrize("waves", [0, 4, 8])
+@pytest.mark.parametrize("waves", [0, 1, 4, 8])
 def test_solve_info_codes(stap, waves):
     D, S, P = 20, 5, 32
     with solve_variant(stap, 1, D, S, "fp32", 0, waves):
@@ -401,7 +403,7 @@ def test_chain_xlarge_sampled(stap, xlarge_cube, precision, refine):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", [16, 8])
+@pytest.mark.parametrize("variant", [16, 8, 1])
 def test_stages_equal_run_and_deterministic(stap, variant):
     """The stage calls and stap_run (fused covariance->solve) give bitwise the
     same power when both use the same solve variant, and runs repeat
@@ -539,15 +541,15 @@ def test_uneven_batch_64_sampled(stap):
 def test_fused_variants_match_oracle(stap, precision, refine):
     """Every solve variant of the fused covariance->solve kernel (the two
     column-sweep thread grids and the blocked matrix-core solve with 4 and 8
-    waves), selected through the tuning table, against the oracle on the
-    48-DOF cube."""
+    waves) and the stage route with the one-wave solve (variant 1), selected
+    through the tuning table, against the oracle on the 48-DOF cube."""
     wl = synth.MEDIUM
     cube = synth.make_cube(wl)
     V = synth.steering(wl)
     o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
     out = {}
     try:
-        for variant in (16, 32, 4, 8):
+        for variant in (16, 32, 4, 8, 1):
             stap.tune_set(wl.dof, wl.n_steer, precision, refine, variant)
             prob = prob_of(wl, precision, refine)
             W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device="cuda")
