@@ -267,12 +267,12 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
         for (int I = 0; I < NB; ++I) {
           doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
           const int c = 16 * I + m;
-#pragma unroll 2
-          for (int J = 0; J < NB; ++J) {
-            float2 rv[4], z[4];
+          // operands of block row J: R[16J + 4q + s4][c] and the lane's
+          // Z_NJ[m][4q + s4]; fetched one step ahead of their MFMAs
+          auto fetch = [&](int J, float2 (&rv)[4], float2 (&z)[4]) {
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
-              const int r = 16 * J + 4 * q + s4;  // R[r][c]
+              const int r = 16 * J + 4 * q + s4;
               if (r < D && c < D) {
                 rv[s4] = r >= c ? Rp[r * (r + 1) / 2 + c] : Rp[c * (c + 1) / 2 + r];
                 if (r < c) rv[s4].y = -rv[s4].y;
@@ -282,6 +282,13 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
               const float2 u = (s < S && r < D) ? W[s * D + r] : make_float2(0.f, 0.f);
               z[s4] = make_float2(u.x, -u.y);
             }
+          };
+          float2 rv[4], z[4];
+          fetch(0, rv, z);
+#pragma unroll 1
+          for (int J = 0; J < NB; ++J) {
+            float2 rn[4], zn[4];
+            fetch(J + 1 < NB ? J + 1 : J, rn, zn);
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
               const double qr = rv[s4].x, qi = rv[s4].y, pr = z[s4].x, pi = z[s4].y;
@@ -289,6 +296,11 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
               cr = mfma64(-qi, pi, cr);
               ci = mfma64(qr, pi, ci);
               ci = mfma64(qi, pr, ci);
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              rv[s4] = rn[s4];
+              z[s4] = zn[s4];
             }
           }
           float re[4], im[4];
