@@ -121,6 +121,91 @@ __device__ __forceinline__ void forward_solve(const Acc (&L)[NB * (NB + 1) / 2],
   }
 }
 
+// The trailing updates of factorisation step J other than the one of
+// diagonal block J+1, numbered 0..COUNT-1: first the L blocks (I, K),
+// K = J+1.., I = K.., then the M blocks (N, K).
+template <int NB, int NS, int J>
+struct StepWork {
+  static constexpr int NLU = (NB - J - 1) * (NB - J) / 2 - (J + 1 < NB ? 1 : 0);
+  static constexpr int COUNT = NLU + (NB - J - 1) * NS;
+  struct Item {
+    bool isL;
+    int I, K, N;
+  };
+  static constexpr Item item(int p) {
+    int n = 0;
+    for (int K = J + 1; K < NB; ++K)
+      for (int I = K; I < NB; ++I) {
+        if (K == J + 1 && I == J + 1) continue;
+        if (n == p) return Item{true, I, K, 0};
+        ++n;
+      }
+    for (int K = J + 1; K < NB; ++K)
+      for (int N = 0; N < NS; ++N) {
+        if (n == p) return Item{false, 0, K, N};
+        ++n;
+      }
+    return Item{false, -1, -1, -1};
+  }
+};
+
+template <int NB, int NS, int J, int P, int END>
+__device__ __forceinline__ void step_work(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB]) {
+  if constexpr (P < END) {
+    constexpr auto it = StepWork<NB, NS, J>::item(P);
+    if constexpr (it.isL) pqh<true>(L[tri(it.I, it.K)], L[tri(it.I, J)], L[tri(it.K, J)]);
+    else pqh<true>(M[it.N * NB + it.K], M[it.N * NB + J], L[tri(it.K, J)]);
+    step_work<NB, NS, J, P + 1, END>(L, M);
+  }
+}
+
+// Columns j.. of diag_factor_inv() with the share of step J's trailing
+// updates that goes with each column issued right after it, so the wave's
+// instruction stream interleaves the serial VALU work of diagonal block
+// J+1 with independent matrix-core products.
+template <int NB, int NS, int J, int j>
+__device__ __forceinline__ void diag_cols_work(Frag& A, Frag& X, int m, float& rsm, int& fail,
+                                               Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB]) {
+  constexpr int C = StepWork<NB, NS, J>::COUNT;
+  diag_col<j>(A, X, m, rsm, fail);
+  step_work<NB, NS, J, j * C / 16, (j + 1) * C / 16>(L, M);
+  if constexpr (j < 15) diag_cols_work<NB, NS, J, j + 1>(A, X, m, rsm, fail, L, M);
+}
+
+// Factorisation step J (diagonal block J already holds Linv_JJ): panel,
+// the update and factorisation of diagonal block J+1 interleaved with the
+// remaining updates of the step, then step J+1.
+template <int NB, int NS, int J>
+__device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB], int& fail) {
+#pragma unroll
+  for (int I = J + 1; I < NB; ++I) {
+    Acc x = acc_zero();
+    pqh<false>(x, L[tri(I, J)], L[tri(J, J)]);
+    L[tri(I, J)] = x;
+  }
+#pragma unroll
+  for (int N = 0; N < NS; ++N) {
+    Acc x = acc_zero();
+    pqh<false>(x, M[N * NB + J], L[tri(J, J)]);
+    M[N * NB + J] = x;
+  }
+  if constexpr (J + 1 < NB) {
+    pqh<true>(L[tri(J + 1, J + 1)], L[tri(J + 1, J)], L[tri(J + 1, J)]);
+    const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+    Frag A = to_frag(L[tri(J + 1, J + 1)]), X;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
+    int f = 0;
+    float rsm = 1.f;
+    diag_cols_work<NB, NS, J, 0>(A, X, m, rsm, f, L, M);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X.v[i] = make_float2(X.v[i].x * rsm, X.v[i].y * rsm);
+    fail = (fail == 0 && f != 0) ? 16 * (J + 1) + f : fail;
+    L[tri(J + 1, J + 1)] = to_acc(X);
+    fact_step<NB, NS, J + 1>(L, M, fail);
+  }
+}
+
 // LDS of one system: transpose slots, then (REFINE) the packed lower
 // triangle of R_L, row r at offset r (r + 1) / 2.
 template <int NB, bool REFINE>
@@ -185,34 +270,13 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
 
   // ---- factorisation with the forward solve of the steering rows
   int fail = 0;
-#pragma unroll
-  for (int J = 0; J < NB; ++J) {
-    {
-      Frag A = to_frag(L[tri(J, J)]), X;
-      const int f = diag_factor_inv(A, X);
-      fail = (fail == 0 && f != 0) ? 16 * J + f : fail;
-      L[tri(J, J)] = to_acc(X);
-    }
-#pragma unroll
-    for (int I = J + 1; I < NB; ++I) {
-      Acc x = acc_zero();
-      pqh<false>(x, L[tri(I, J)], L[tri(J, J)]);
-      L[tri(I, J)] = x;
-    }
-#pragma unroll
-    for (int N = 0; N < NS; ++N) {
-      Acc x = acc_zero();
-      pqh<false>(x, M[N * NB + J], L[tri(J, J)]);
-      M[N * NB + J] = x;
-    }
-#pragma unroll
-    for (int K = J + 1; K < NB; ++K) {
-#pragma unroll
-      for (int I = K; I < NB; ++I) pqh<true>(L[tri(I, K)], L[tri(I, J)], L[tri(K, J)]);
-#pragma unroll
-      for (int N = 0; N < NS; ++N) pqh<true>(M[N * NB + K], M[N * NB + J], L[tri(K, J)]);
-    }
+  {
+    Frag A = to_frag(L[0]), X;
+    const int f = diag_factor_inv(A, X);
+    fail = f != 0 ? f : 0;
+    L[0] = to_acc(X);
   }
+  fact_step<NB, NS, 0>(L, M, fail);
   if (fail) {
     for (int e = lane; e < S * D; e += 64) W[e] = make_float2(0.f, 0.f);
     if (lane == 0 && info) *info = fail;

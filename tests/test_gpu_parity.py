@@ -147,6 +147,7 @@ def _solve_case(wl):
 
 
 SOLVE_SHAPES = TINY + [(4, 64, 512, 3, 32, 8), (16, 128, 1024, 3, 16, 16),
+                       (22, 32, 256, 3, 2, 31), (28, 32, 256, 3, 2, 27),
                        (32, 32, 256, 3, 2, 32), (32, 32, 256, 3, 2, 64),
                        (40, 32, 256, 3, 2, 20), (48, 32, 256, 3, 2, 20),
                        (64, 32, 256, 3, 2, 64), (60, 32, 512, 3, 2, 33)]
