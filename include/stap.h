@@ -166,7 +166,10 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
  * over every (cube, bin, block) system ordered by cost, and one
  * inner-product launch; the problem table (n_probs * 128 bytes) is copied
  * from the host into the workspace and the launch chain is replayed from a
- * cached hipGraph.  Calls that overlap on one workspace race. */
+ * cached hipGraph.  A single cube runs Doppler, the fused covariance->solve
+ * (or, where the tuning table selects kind-0 variant 1 or the shape is not
+ * fused-eligible, the stage covariance and a stage solve), and the inner
+ * products.  Calls that overlap on one workspace race. */
 stap_status stap_run(const stap_problem* probs, int32_t n_probs,
                      const stap_cf32* const* cubes,
                      const stap_cf32* const* steers, float* const* powers,
@@ -202,7 +205,9 @@ int32_t stap_tune_get(int32_t kind, int32_t dof, int32_t n_steer, int32_t precis
  * launched directly into that capture. */
 void stap_use_graphs(int32_t enable);
 
-/* Bytes of device workspace stap_run needs for these problems; 0 on invalid
+/* Bytes of device workspace stap_run needs for these problems (per cube:
+ * snapshots, weights and info, plus the covariance and delta for D > 128,
+ * FP8, or D <= 96 with S <= 32); 0 on invalid
  * arguments. */
 size_t stap_workspace_size(const stap_problem* probs, int32_t n_probs);
 
