@@ -127,17 +127,8 @@ __device__ __forceinline__ void mma_pq(Acc& x, const Frag& P, const Frag& Qt) {
   }
 }
 
-// Broadcast 16-lane row R of v to all four rows with the gfx950 lane
-// swaps: the 32-lane swap of v with itself returns rows (0, 1, 0, 1) and
-// (2, 3, 2, 3); the 16-lane swap of either with itself returns its even row
-// and its odd row, each in all four rows.
-template <int R>
-__device__ __forceinline__ float xrowb(float v) {
-  const unsigned u = __float_as_uint(v);
-  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-  const unsigned hv = h[R >> 1];
-  const auto b = __builtin_amdgcn_permlane16_swap(hv, hv, false, false);
-  return __uint_as_float(b[R & 1]);
+__device__ __forceinline__ float2 shfl2(float2 v, int src) {
+  return make_float2(__shfl(v.x, src), __shfl(v.y, src));
 }
 __device__ __forceinline__ float bcast(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -169,7 +160,7 @@ __device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, float& rsm, in
   const float piv = bcast(A.v[ji].x, j + 16 * jq);  // A[j][j], wave-uniform
   fail = (fail == 0 && !(piv > 0.f)) ? j + 1 : fail;
   const float rs = __builtin_amdgcn_rsqf(piv), r2 = rs * rs;
-  const float2 amj = make_float2(xrowb<jq>(A.v[ji].x), xrowb<jq>(A.v[ji].y));  // A[m][j]
+  const float2 amj = shfl2(A.v[ji], m + 16 * jq);  // A[m][j]
   const float2 la = make_float2(amj.x * r2, amj.y * r2);  // l_mj / d_j
   const float2 lx = (m > j) ? la : make_float2(0.f, 0.f);
   rsm = (m == j) ? rs : rsm;

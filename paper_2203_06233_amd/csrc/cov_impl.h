@@ -108,28 +108,51 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
     qscale = ldexpf(1.f, 8 - ex);     // largest magnitude lands in [128, 256)
   }
 
-  for (int c0 = 0; c0 < N; c0 += kCovChunk) {
+  // Staging is double-buffered through registers: the global loads of chunk
+  // c + 1 are issued before the products of chunk c, so their latency hides
+  // behind the matrix-core work.  MODE 0 / 2: element e = tid + NT i is
+  // (row e / 32, cell e % 32); MODE 1: pair e is (row e / 16, cells 2 (e % 16)
+  // and 2 (e % 16) + 1).
+  constexpr int NE = MODE == 1 ? DP * (kCovChunk / 2) : DP * kCovChunk;
+  constexpr int PF = (NE + NT - 1) / NT;
+  constexpr int PV = MODE == 1 ? 2 : 1;
+  float2 pf[PF][PV];
+  auto load_chunk = [&](int c0) {
     const int nc = min(kCovChunk, N - c0);
-    __syncthreads();
-    if (MODE == 0) {
-      float2* xs = reinterpret_cast<float2*>(lds);
-      for (int e = tid; e < DP * kCovChunk; e += NT) {
-        const int row = e / kCovChunk, cc = e % kCovChunk;
-        float2 v = make_float2(0.f, 0.f);
-        if (row < D && cc < nc) v = X[(long long)row * rstride + c0 + cc];
-        xs[row * F32_PITCH + cc] = v;
-      }
-    } else if (MODE == 1) {
-      unsigned int* pl = reinterpret_cast<unsigned int*>(lds);
-      constexpr int PS = DP * BF_PITCH / 2;  // plane stride, uint32
-      for (int e = tid; e < DP * (kCovChunk / 2); e += NT) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + NT * i;
+      if (MODE == 1) {
         const int row = e / (kCovChunk / 2), cp = e % (kCovChunk / 2);
         float2 v0 = make_float2(0.f, 0.f), v1 = v0;
-        if (row < D) {
+        if (e < NE && row < D) {
           const float2* src = X + (long long)row * rstride + c0 + 2 * cp;
           if (2 * cp < nc) v0 = src[0];
           if (2 * cp + 1 < nc) v1 = src[1];
         }
+        pf[i][0] = v0;
+        pf[i][PV - 1] = v1;
+      } else {
+        const int row = e / kCovChunk, cc = e % kCovChunk;
+        float2 v = make_float2(0.f, 0.f);
+        if (e < NE && row < D && cc < nc) v = X[(long long)row * rstride + c0 + cc];
+        pf[i][0] = v;
+      }
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = tid + NT * i;
+      if (e >= NE) continue;
+      if (MODE == 0) {
+        float2* xs = reinterpret_cast<float2*>(lds);
+        xs[(e / kCovChunk) * F32_PITCH + e % kCovChunk] = pf[i][0];
+      } else if (MODE == 1) {
+        unsigned int* pl = reinterpret_cast<unsigned int*>(lds);
+        constexpr int PS = DP * BF_PITCH / 2;  // plane stride, uint32
+        const int row = e / (kCovChunk / 2), cp = e % (kCovChunk / 2);
+        const float2 v0 = pf[i][0], v1 = pf[i][PV - 1];
         unsigned int h, m, l;
         const int base = row * (BF_PITCH / 2) + cp;
         split3x2(v0.x, v1.x, h, m, l);
@@ -140,18 +163,22 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
         pl[3 * PS + base] = h;
         pl[4 * PS + base] = m;
         pl[5 * PS + base] = l;
-      }
-    } else {
-      unsigned char* pl = lds;
-      for (int e = tid; e < DP * kCovChunk; e += NT) {
+      } else {
+        unsigned char* pl = lds;
         const int row = e / kCovChunk, cc = e % kCovChunk;
-        float2 v = make_float2(0.f, 0.f);
-        if (row < D && cc < nc) v = X[(long long)row * rstride + c0 + cc];
-        pl[row * F8_PITCH + cc] = (unsigned char)f2e4m3(v.x * qscale);
-        pl[DP * F8_PITCH + row * F8_PITCH + cc] = (unsigned char)f2e4m3(v.y * qscale);
+        pl[row * F8_PITCH + cc] = (unsigned char)f2e4m3(pf[i][0].x * qscale);
+        pl[DP * F8_PITCH + row * F8_PITCH + cc] = (unsigned char)f2e4m3(pf[i][0].y * qscale);
       }
     }
+  };
+
+  load_chunk(0);
+  for (int c0 = 0; c0 < N; c0 += kCovChunk) {
+    const int nc = min(kCovChunk, N - c0);
+    __syncthreads();  // the previous chunk's products are done with the staging buffer
+    store_chunk();
     __syncthreads();
+    if (c0 + kCovChunk < N) load_chunk(c0 + kCovChunk);
 
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {

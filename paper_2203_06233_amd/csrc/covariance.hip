@@ -16,8 +16,11 @@ namespace stap {
 
 namespace {
 
+// Up to 96 DOF on 8 waves the register allocation is capped at 128, two
+// workgroups per compute unit.
 template <int DP, int NW, int MODE>
-__global__ __launch_bounds__(NW * 64) void cov_kernel(const float2* __restrict__ snap,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(DP <= 96 && NW == 8 ? 4 : 1)))
+void cov_kernel(const float2* __restrict__ snap,
                                                       float2* __restrict__ cov,
                                                       float* __restrict__ delta_out, Dims d) {
   using Cfg = CovCfg<DP, NW, MODE>;

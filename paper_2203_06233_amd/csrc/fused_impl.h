@@ -116,13 +116,14 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
                            d, lds + (REFINE ? PACK : 0));
 }
 
-// With refinement and 8 waves the register allocation is capped at 128 so
-// that two systems share a compute unit (a few registers spill).
-template <int NW, bool REFINE>
-constexpr int bfused_min_waves() { return REFINE && NW == 8 ? 4 : 1; }
+// With 8 waves and up to 6 block columns the register allocation is capped
+// at 128 so that two systems share a compute unit (with refinement a few
+// registers spill).
+template <int NB, int NW>
+constexpr int bfused_min_waves() { return NW == 8 && NB <= 6 ? 4 : 1; }
 
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NW, REFINE>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NW>())))
 void bfused_kernel(const float2* __restrict__ snap,
                                                          const float2* __restrict__ steer,
                                                          float2* __restrict__ wout, int* __restrict__ info_out,
@@ -131,7 +132,7 @@ void bfused_kernel(const float2* __restrict__ snap,
 }
 
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NW, REFINE>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NW>())))
 void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
                                                                  long long total) {
   for (long long g = blockIdx.x; g < total; g += gridDim.x) {

@@ -85,23 +85,6 @@ __device__ __forceinline__ void back_solve(const Acc (&L)[NB * (NB + 1) / 2], Ac
   }
 }
 
-// Lane (m, q) register i holds element (m, q + 4i) of a block; reorder into
-// fragment order, register i holding (m, 4q + i).  For each m this is the
-// transpose of a 4 x 4 grid (rows of the wave x registers): the gfx950
-// 32-lane swaps exchange the upper row pair of registers 0 / 1 with the
-// lower row pair of registers 2 / 3, then the 16-lane swaps exchange the odd
-// rows of registers 0 / 2 with the even rows of registers 1 / 3.
-__device__ __forceinline__ void qi_transpose(float (&v)[4]) {
-  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[0]), __float_as_uint(v[2]), false, false);
-  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[1]), __float_as_uint(v[3]), false, false);
-  const auto c = __builtin_amdgcn_permlane16_swap(a[0], b[0], false, false);
-  const auto e = __builtin_amdgcn_permlane16_swap(a[1], b[1], false, false);
-  v[0] = __uint_as_float(c[0]);
-  v[1] = __uint_as_float(c[1]);
-  v[2] = __uint_as_float(e[0]);
-  v[3] = __uint_as_float(e[1]);
-}
-
 // Forward solve Y^H L^H = M with the factor in L (Linv_JJ on the diagonal):
 // M_J := M_J Linv_JJ^H, then M_K -= M_J L_KJ^H for K > J.
 template <int NB, int NS>
@@ -323,7 +306,7 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
       // FP32 values): block (N, I) sums Z_NJ R_JI over J.  The lane's Z
       // operand is its own element Z_NJ[m][4q + s4], read back from W; R
       // comes from the packed copy.  The FP64 result has column q + 4i of
-      // the block in register i; qi_transpose() restores fragment order.
+      // the block in register i; a pass through tb restores fragment order.
 #pragma unroll
       for (int N = 0; N < NS; ++N) {
         const int s = 16 * N + m;
@@ -367,21 +350,15 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
               z[s4] = zn[s4];
             }
           }
-          float re[4], im[4];
+          __syncthreads();  // earlier reads of tb are done
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int k = 16 * I + q + 4 * i;
             const float2 v = (s < S && k < D) ? steer[s * D + k] : make_float2(0.f, 0.f);
-            re[i] = (float)((double)v.x - cr[i]);
-            im[i] = (float)(-(double)v.y - ci[i]);
+            tb[bofs(m, q + 4 * i)] = make_float2((float)((double)v.x - cr[i]), (float)(-(double)v.y - ci[i]));
           }
-          qi_transpose(re);
-          qi_transpose(im);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            M[N * NB + I].re[i] = re[i];
-            M[N * NB + I].im[i] = im[i];
-          }
+          __syncthreads();
+          M[N * NB + I] = to_acc(frag_load(tb));
         }
       }
       forward_solve<NB, NS>(L, M);
