@@ -140,6 +140,22 @@ def test_tuning_table(binding):
     assert lib.stap_tune_set(1, 96, 32, 1, 0, 0) == 0
     assert lib.stap_tune_set(0, 200, 32, 1, 1, 16) == -1
     assert lib.stap_tune_get(0, 96, 65, 1, 1) == -1
+    # variant 1 (one wave per system) is a valid entry for both kinds
+    for kind in (0, 1):
+        old = lib.stap_tune_get(kind, 96, 32, 1, 0)
+        assert lib.stap_tune_set(kind, 96, 32, 1, 0, 1) == 0 and lib.stap_tune_get(kind, 96, 32, 1, 0) == 1
+        assert lib.stap_tune_set(kind, 96, 32, 1, 0, old) == 0
+    assert lib.stap_tune_set(0, 96, 32, 1, 0, 2) == -1
+
+
+def test_tuner_candidates():
+    """The autotuner times the one-wave solve only where it applies."""
+    from paper_2203_06233_amd import tune
+    assert 1 in tune.candidates(96, 0, 0, 32) and 1 in tune.candidates(12, 1, 1, 8)
+    assert 1 not in tune.candidates(112, 0, 0, 32)  # D > 96
+    assert 1 not in tune.candidates(96, 0, 0, 33)  # S > 32
+    assert tune.candidates(192, 1, 1, 64) == [0, 8]
+    assert 32 not in tune.candidates(32, 0)  # the 32-row grid needs D > 32
 
 
 def test_workspace_size_formula(binding):
