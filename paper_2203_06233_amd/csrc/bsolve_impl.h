@@ -274,11 +274,14 @@ __device__ __forceinline__ float2 reload(const float2* p) {
 // residual reads it again).  xlds points at lds_bytes(NB, NS) of 16-byte
 // aligned LDS, which may overlap the source only without REFINE (the source
 // is read completely before the first write).  W is this system's [S][D]
-// output, info its status word (may be null).
+// output, info its status word (may be null).  park (may be null) is LDS of
+// at least 16 NS x 16 NB complex that is free once the last residual has
+// been formed (the source, when it lives in LDS): the last refinement step
+// keeps u there instead of in W.
 template <class C, bool REFINE, class RSrc>
 __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __restrict__ steer,
                                               float2* __restrict__ W, int* __restrict__ info, const Dims& d,
-                                              unsigned char* xlds) {
+                                              unsigned char* xlds, float2* park = nullptr) {
   constexpr int NSL = C::NSL, NSM = C::NSM, NW = C::NW;
   const int D = d.D, S = d.S;
   const int NB = (D + 15) >> 4, NS = (S + 15) >> 4;
@@ -463,11 +466,12 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
 
   if (REFINE) {
     for (int it = 0; it < d.refine; ++it) {
+      const bool lds_park = park != nullptr && it == d.refine - 1;
       // keep the current u = conj(Z) in W (this lane's own elements; read
-      // back by the same lane after the correction)
+      // back by the same lane after the correction), or in park
 #pragma unroll
       for (int t = 0; t < NSM; ++t) {
-        if (mv[t]) {
+        if (mv[t] && !lds_park) {
           const int s = 16 * mr[t] + m;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -524,14 +528,17 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
       }
       __syncthreads();  // every Z block has been read
       // conj(r) rounded to FP32, back into fragment order through the
-      // block's own (now free) Z position
+      // block's own (now free) Z position, or through its park slot, which
+      // then takes the Z block itself (u for the correction)
 #pragma unroll
       for (int t = 0; t < NSM; ++t) {
         if (mv[t]) {
-          float2* tb = xb + (mr[t] * NB + mc[t]) * 256;
+          float2* zb = xb + (mr[t] * NB + mc[t]) * 256;
+          float2* tb = lds_park ? park + (mr[t] * NB + mc[t]) * 256 : zb;
 #pragma unroll
           for (int i = 0; i < 4; ++i) tb[bofs(m, q + 4 * i)] = make_float2(am[t].re[i], am[t].im[i]);
           am[t] = to_acc(frag_load(tb));
+          if (lds_park) frag_store(tb, frag_load(zb));
         }
       }
       // forward solve Y^H L^H = r^H with the stored factor
@@ -558,10 +565,14 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
             mma_pqh<true>(am[t], frag_load(xb + (NB + mr[t]) * 256), frag_load(xb + mc[t] * 256));
       }
       back_solve();
-      // Z += the correction (u kept in W)
+      // Z += the correction (u kept in W or park)
 #pragma unroll
       for (int t = 0; t < NSM; ++t) {
-        if (mv[t]) {
+        if (mv[t] && lds_park) {
+          const Acc z = to_acc(frag_load(park + (mr[t] * NB + mc[t]) * 256));
+          am[t].re += z.re;
+          am[t].im += z.im;
+        } else if (mv[t]) {
           const int s = 16 * mr[t] + m;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {

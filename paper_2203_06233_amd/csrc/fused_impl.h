@@ -112,8 +112,11 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
   float2* Rp = reinterpret_cast<float2*>(lds);
   cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
   __syncthreads();
+  // the packed R_L is dead after the last residual: u of that step is kept
+  // there when it fits
+  constexpr bool PARK = REFINE && PACK >= NS * NB * 256 * 8;
   bsolve_system<B, REFINE>(PackedR{Rp}, steer, wout + (long long)sys * d.S * D, info_out ? info_out + sys : nullptr,
-                           d, lds + (REFINE ? PACK : 0));
+                           d, lds + (REFINE ? PACK : 0), PARK ? Rp : nullptr);
 }
 
 // With 8 waves and up to 6 block columns the register allocation is capped
