@@ -25,8 +25,14 @@ paper leaves open, each chosen once and used on both sides:
   L = P - T + 1 placed at pulses t .. t+L-1, then a length-P DFT with kernel
   exp(-j 2 pi k p / P), unnormalised, bins in natural order; DOF index
   d = t*C + c.
+* Tap phase reference: absolute pulse index in the DFT kernel (default), or
+  each tap referenced to its own first pulse (relative), in which case an
+  on-bin target at bin k carries the temporal phase exp(j 2 pi k t / P) in tap
+  t and the steering set is given per bin.
 * Training: B contiguous blocks of N = R/B range cells; block b's covariance
-  is the mean outer product of its own snapshots (cell under test included).
+  is the mean outer product of its own snapshots (cell under test included),
+  or, as in standard STAP practice, of the N nearest cells outside the block
+  and G guard cells on each side (cell under test excluded).
 * Loading: delta = eps * Re tr(R_hat) / D added to the diagonal.
 * Weights: adaptive matched filter, w = R_L^-1 v / sqrt(v^H R_L^-1 v).
 * Output: y = w^H x per cell, power |y|^2.
@@ -57,29 +63,67 @@ def tap_windows(P: int, T: int) -> np.ndarray:
     return W
 
 
-def doppler(cube: np.ndarray, T: int) -> np.ndarray:
+def doppler(cube: np.ndarray, T: int, relative: bool = False) -> np.ndarray:
     """Doppler filtering (statements S and T): snapshots ``X[k][t*C + c][r]``.
 
-    X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k p / P).
+    Absolute phase reference (default):
+        X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k p / P).
+    Relative phase reference (``relative``): every tap's DFT is referenced to
+    its own first pulse, i.e. the length-P DFT of the windowed sub-CPI
+    h[n] x[c][t+n][r], n = 0..L-1, zero-padded:
+        X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k (p - t) / P).
     """
     C, P, R = cube.shape
     x = cube.astype(np.complex128)
-    W = tap_windows(P, T)
     X = np.empty((P, T * C, R), np.complex128)
+    if relative:
+        L = P - T + 1
+        h = hann(L)
+        for t in range(T):
+            sub = np.zeros((C, P, R), np.complex128)
+            sub[:, :L, :] = x[:, t:t + L, :] * h[None, :, None]
+            X[:, t * C:(t + 1) * C, :] = np.fft.fft(sub, axis=1).transpose(1, 0, 2)
+        return X
+    W = tap_windows(P, T)
     for t in range(T):
         Xt = np.fft.fft(x * W[t][None, :, None], axis=1)  # [C][k][R]
         X[:, t * C:(t + 1) * C, :] = Xt.transpose(1, 0, 2)
     return X
 
 
-def covariance(X: np.ndarray, n_block: int) -> np.ndarray:
+def training_cells(n_range: int, n_block: int, b: int, guard: int) -> np.ndarray:
+    """Range cells that train block b when the cells under test are excluded.
+
+    Block b holds cells [bN, bN + N).  Those cells and ``guard`` cells on each
+    side are excluded; the N training cells are the nearest remaining ones,
+    half (rounded down) on the left and the rest on the right, moved to the
+    other side where a side runs out of cells at the edge of the cube.  Needs
+    R >= 2N + 2G so that every block has N cells to train on.
+    """
+    R, N, G = n_range, n_range // n_block, guard
+    lo, hi = b * N - G, b * N + N + G          # excluded cells [lo, hi)
+    left_avail, right_avail = max(0, lo), max(0, R - hi)
+    if left_avail + right_avail < N:
+        raise ValueError("not enough range cells outside the guard region")
+    n_right = min(N - min(N // 2, left_avail), right_avail)
+    n_left = N - n_right
+    return np.concatenate([np.arange(lo - n_left, lo), np.arange(hi, hi + n_right)])
+
+
+def covariance(X: np.ndarray, n_block: int, guard: Optional[int] = None) -> np.ndarray:
     """Sample covariance per (Doppler bin, training block) (statement U).
 
-    R_hat[k][b] = (1/N) sum_{r in block b} X[k][:, r] X[k][:, r]^H.
+    R_hat[k][b] = (1/N) sum_{r in Omega_b} X[k][:, r] X[k][:, r]^H, with
+    Omega_b the block's own N cells (``guard`` None: the cell under test is
+    part of its training set) or, with ``guard`` = G >= 0, the N cells of
+    ``training_cells`` (the block and G guard cells on each side excluded).
     """
     P, D, R = X.shape
     N = R // n_block
-    Xb = X.reshape(P, D, n_block, N).transpose(0, 2, 1, 3)  # [k][b][d][n]
+    if guard is None:
+        Xb = X.reshape(P, D, n_block, N).transpose(0, 2, 1, 3)  # [k][b][d][n]
+    else:
+        Xb = np.stack([X[:, :, training_cells(R, n_block, b, guard)] for b in range(n_block)], axis=1)
     return (Xb @ np.conj(Xb).swapaxes(-1, -2)) / N
 
 
@@ -116,7 +160,9 @@ def cholesky_info(A: np.ndarray):
 def solve_weights(R_L: np.ndarray, V: np.ndarray):
     """Adaptive matched-filter weights for every system and steering vector.
 
-    R_L ``[..][D][D]`` loaded covariances, V ``[S][D]`` steering set.
+    R_L ``[..][D][D]`` loaded covariances, V ``[S][D]`` steering set shared
+    by every system, or ``[P][S][D]`` with one set per Doppler bin (then R_L is
+    ``[P][B][D][D]`` and bin k's systems use V[k]).
     u_s = R_L^-1 v_s; gamma_s = Re(v_s^H u_s); w_s = u_s / sqrt(gamma_s).
     The weights are defined by the solve, so a general dense solve
     (``numpy.linalg.solve``) computes them; the Cholesky factorisation is used
@@ -124,6 +170,9 @@ def solve_weights(R_L: np.ndarray, V: np.ndarray):
     index of the first pivot that is not positive, and those systems get zero
     weights.  Returns (W ``[..][S][D]``, gamma ``[..][S]``, info ``[..]``).
     """
+    if V.ndim == 3:
+        parts = [solve_weights(R_L[k], V[k]) for k in range(V.shape[0])]
+        return tuple(np.stack([p[i] for p in parts]) for i in range(3))
     batch = R_L.shape[:-2]
     D = R_L.shape[-1]
     S = V.shape[0]
@@ -160,10 +209,11 @@ def inner_products(W: np.ndarray, X: np.ndarray, n_block: int):
 
 
 def run(cube: np.ndarray, V: np.ndarray, T: int, n_block: int, eps: float,
-        keep: bool = True) -> Dict[str, np.ndarray]:
-    """The whole chain on one cube ``[C][P][R]`` with steering set ``[S][D]``."""
-    X = doppler(cube, T)
-    R_hat = covariance(X, n_block)
+        keep: bool = True, relative: bool = False, guard: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """The whole chain on one cube ``[C][P][R]`` with steering set ``[S][D]``
+    (or ``[P][S][D]`` per bin)."""
+    X = doppler(cube, T, relative)
+    R_hat = covariance(X, n_block, guard)
     delta, R_L = loading(R_hat, eps)
     W, gamma, info = solve_weights(R_L, V)
     y, power = inner_products(W, X, n_block)
@@ -174,21 +224,30 @@ def run(cube: np.ndarray, V: np.ndarray, T: int, n_block: int, eps: float,
 
 
 def run_block(cube_block: np.ndarray, V: np.ndarray, T: int, eps: float,
-              bins: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+              bins: Optional[np.ndarray] = None, relative: bool = False,
+              train_block: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """The chain for ONE training block: ``cube_block`` is ``[C][P][N]``.
 
     Doppler filtering acts on each (channel, range cell) column alone, so the
     block's snapshots need only its own cells; ``bins`` selects Doppler bins.
-    Returns arrays indexed [k][...] over the selected bins with B = 1.
+    ``train_block`` (``[C][P][N]``, the cube at the block's training cells,
+    e.g. ``training_cells``) trains the covariance instead of the block
+    itself.  V is ``[S][D]`` or ``[P][S][D]``.  Returns arrays indexed [k][...]
+    over the selected bins with B = 1.
     """
-    X = doppler(cube_block, T)
+    X = doppler(cube_block, T, relative)
+    Xt = None if train_block is None else doppler(train_block, T, relative)
     if bins is not None:
         X = X[np.asarray(bins)]
-    return run_from_snapshots(X, V, 1, eps)
+        Xt = None if Xt is None else Xt[np.asarray(bins)]
+        if V.ndim == 3:
+            V = V[np.asarray(bins)]
+    return run_from_snapshots(X, V, 1, eps, X_train=Xt)
 
 
-def run_from_snapshots(X: np.ndarray, V: np.ndarray, n_block: int, eps: float):
-    R_hat = covariance(X, n_block)
+def run_from_snapshots(X: np.ndarray, V: np.ndarray, n_block: int, eps: float,
+                       X_train: Optional[np.ndarray] = None):
+    R_hat = covariance(X if X_train is None else X_train, n_block)
     delta, R_L = loading(R_hat, eps)
     W, gamma, info = solve_weights(R_L, V)
     y, power = inner_products(W, X, n_block)

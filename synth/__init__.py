@@ -56,6 +56,7 @@ class Workload:
     n_scat: int = 32
     seed: int = 1000
     cube_index: int = 0
+    target_offset: float = 0.0   # target Doppler off its bin, in bins (0 = on-bin)
 
     @property
     def dof(self) -> int:
@@ -112,7 +113,7 @@ class Scene:
     scat_theta: np.ndarray   # [n_scat] spatial frequency, cycles per element
     scat_doppler: np.ndarray  # [n_scat] normalised Doppler, cycles per pulse
     target_steer: int        # index s_t into the steering set
-    target_bin: int          # Doppler bin k_t (on-bin: doppler = k_t / P)
+    target_bin: int          # Doppler bin k_t (doppler = (k_t + target_offset) / P)
     target_cell: int         # range cell r_t
     target_amp: complex      # complex amplitude a, |a|^2 = SNR
 
@@ -156,7 +157,7 @@ def _chunk(wl: Workload, sc: Scene, chunk: int) -> np.ndarray:
     x = noise + (basis @ alpha).reshape(C, P, n)
     if r0 <= sc.target_cell < r0 + n:
         th_t = steer_theta(wl.n_steer)[sc.target_steer]
-        f_t = sc.target_bin / P
+        f_t = (sc.target_bin + wl.target_offset) / P
         tgt = sc.target_amp * np.exp(2j * np.pi * (th_t * np.arange(C)[:, None] + f_t * np.arange(P)[None, :]))
         x[:, :, sc.target_cell - r0] += tgt
     return x.astype(np.complex64)
@@ -188,6 +189,19 @@ def steering(wl: Workload) -> np.ndarray:
     th = steer_theta(wl.n_steer)
     spatial = np.exp(2j * np.pi * th[:, None] * np.arange(wl.n_chan)[None, :])
     return np.tile(spatial, (1, wl.tdof)).astype(np.complex64)
+
+
+def steering_per_bin(wl: Workload) -> np.ndarray:
+    """Steering set per Doppler bin ``[P][S][D]`` complex64 for taps that are
+    each referenced to their own first pulse: v_{k,s}[t*C + c] =
+    exp(j 2 pi k t / P) exp(j 2 pi theta_s c).  A target on bin k then carries
+    the temporal phase exp(j 2 pi k t / P) across the taps.
+    """
+    P, T = wl.n_pulse, wl.tdof
+    spatial = steering(wl)[:, :wl.n_chan].astype(np.complex128)          # [S][C]
+    ramp = np.exp(2j * np.pi * np.outer(np.arange(P), np.arange(T)) / P)  # [P][T]
+    V = ramp[:, None, :, None] * spatial[None, :, None, :]               # [P][S][T][C]
+    return V.reshape(P, wl.n_steer, T * wl.n_chan).astype(np.complex64)
 
 
 def with_(wl: Workload, **kw) -> Workload:

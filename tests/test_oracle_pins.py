@@ -275,16 +275,243 @@ def check_block_sampling(orc=stap, res=None):
                                    rtol=1e-9, atol=1e-12)
 
 
+# ------------------------------------------------------------------ error metrics
+#
+# The metrics decide every parity verdict, so they are pinned by hand-computed
+# values: vectors of known norm, a block-diagonal batch, and the SINR of a
+# diagonal covariance in closed form.
+
+def check_rel_err_known_norms(met=metrics):
+    ref = np.array([3.0, 4.0j])                 # ||ref|| = 5
+    a = ref + np.array([0.0, 1.0])              # ||a - ref|| = 1
+    assert abs(met.rel_err(a, ref) - 0.2) < 1e-15
+    # a second error of norm 13 on a reference of norm 13 (5-12-13 triangle)
+    ref2 = np.array([[5.0, 0.0], [0.0, 12.0j]])
+    a2 = ref2 + np.array([[0.0, 12.0], [5.0j, 0.0]])
+    assert abs(met.rel_err(a2, ref2) - 1.0) < 1e-15
+    # a zero reference returns the absolute norm of the difference
+    assert abs(met.rel_err(np.array([3.0, 4.0]), np.zeros(2)) - 5.0) < 1e-15
+
+
+def check_per_system_rel_err_block_diagonal(met=metrics):
+    S, D = 2, 3
+    W_o = np.ones((3, S, D), complex)           # every system: norm sqrt(6)
+    W = W_o.copy()
+    W[0, 0, 0] += 0.6                           # system 0: 0.6 / sqrt(6)
+    W[1] *= 2.0                                 # system 1: 1
+    # system 2 exact
+    got = met.per_system_rel_err(W, W_o)
+    np.testing.assert_allclose(got, [0.6 / math.sqrt(6.0), 1.0, 0.0], rtol=0, atol=1e-15)
+    # a system with zero reference reports its absolute norm
+    Wz = np.zeros((1, S, D), complex)
+    Wz2 = Wz.copy()
+    Wz2[0, 1, 2] = 3.0 + 4.0j
+    np.testing.assert_allclose(met.per_system_rel_err(Wz2, Wz), [5.0], rtol=0, atol=1e-15)
+
+
+def check_sinr_closed_form(met=metrics):
+    """R = sigma^2 I: SINR(w) = |w^H v|^2 / (sigma^2 ||w||^2), = ||v||^2 / sigma^2
+    for w proportional to v.  Diagonal R = diag(r): SINR(R^-1 v) = sum |v_i|^2 / r_i,
+    SINR(v) = ||v||^4 / sum r_i |v_i|^2."""
+    v = np.array([[1.0, 2.0j, -2.0]])           # ||v||^2 = 9
+    sig2 = 2.5
+    R = sig2 * np.eye(3)[None]
+    np.testing.assert_allclose(met.sinr((0.7 - 0.2j) * v[None], v, R), [[9.0 / 2.5]], rtol=1e-14)
+    w = np.array([[[1.0, 0.0, 0.0]]])           # |w^H v|^2 = 1, ||w|| = 1
+    np.testing.assert_allclose(met.sinr(w, v, R), [[1.0 / 2.5]], rtol=1e-14)
+    r = np.array([1.0, 4.0, 0.5])
+    Rd = np.diag(r)[None]
+    w_opt = (v / r)[None]
+    np.testing.assert_allclose(met.sinr(w_opt, v, Rd), [[1.0 + 4.0 / 4.0 + 4.0 / 0.5]], rtol=1e-14)
+    np.testing.assert_allclose(met.sinr(v[None], v, Rd), [[81.0 / (1.0 + 16.0 + 2.0)]], rtol=1e-14)
+
+
+def check_sinr_loss_closed_form(met=metrics):
+    """w = v against w_o = R^-1 v under R = diag(1, 4) and v = (1, 1):
+    SINR(w_o) = 1 + 1/4 = 1.25, SINR(v) = 4 / 5, loss = 10 log10(1.5625)."""
+    v = np.array([[1.0, 1.0]])
+    R = np.diag([1.0, 4.0])[None]
+    w_o = np.array([[[1.0, 0.25]]])
+    loss = met.sinr_loss_db(v[None], w_o, v, R)
+    np.testing.assert_allclose(loss, [[1.9382002601611283]], rtol=1e-13)
+    # the loss is invariant to a complex scale of either weight vector
+    loss2 = met.sinr_loss_db((2.0 - 1.0j) * v[None], 0.5j * w_o, v, R)
+    np.testing.assert_allclose(loss2, loss, rtol=1e-13)
+    np.testing.assert_allclose(met.sinr_loss_db(w_o, w_o, v, R), [[0.0]], atol=1e-14)
+
+
+# ----------------------------------- relative tap phase, per-bin steering (f4)
+
+def check_doppler_relative_brute_force(orc=stap):
+    """Each tap referenced to its own first pulse:
+    X[k][t*C+c][r] = sum_{p=t}^{t+L-1} h[p-t] x[c][p][r] e^{-j 2 pi k (p-t)/P}."""
+    C, P, R, T = 2, 8, 3, 3
+    x = _crandn(_rng(11), C, P, R)
+    L = P - T + 1
+    h = np.hanning(L)
+    X = orc.doppler(x, T, relative=True)
+    for k in range(P):
+        for t in range(T):
+            for c in range(C):
+                for r in range(R):
+                    acc = 0j
+                    for p in range(t, t + L):
+                        acc += h[p - t] * x[c, p, r] * cmath.exp(-2j * math.pi * k * (p - t) / P)
+                    assert abs(X[k, t * C + c, r] - acc) < 1e-12
+
+
+def check_relative_chain_equivalence(orc=stap):
+    """Relative taps are the absolute ones times exp(j 2 pi k t / P), so the
+    covariance becomes Phi R Phi^H with Phi = diag(exp(j 2 pi k t / P)); with
+    the steering set carried through the same phases (per bin) the weights
+    are Phi w and the output power is unchanged."""
+    wl = synth.with_(synth.SMALL, n_range=128, n_block=8)
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    Vk = synth.steering_per_bin(wl).astype(np.complex128)
+    P, C, T = wl.n_pulse, wl.n_chan, wl.tdof
+    phi = np.exp(2j * np.pi * np.outer(np.arange(P), np.repeat(np.arange(T), C)) / P)  # [P][D]
+    np.testing.assert_allclose(Vk, phi[:, None, :] * V[None].astype(np.complex128), atol=2e-7)
+    a = orc.run(cube, V, T, wl.n_block, wl.load_eps)
+    b = orc.run(cube, phi[:, None, :] * V[None].astype(np.complex128), T, wl.n_block, wl.load_eps,
+                relative=True)
+    np.testing.assert_allclose(b["X"], phi[:, :, None] * a["X"], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(b["W"], phi[:, None, None, :] * a["W"], rtol=1e-8, atol=1e-12)
+    np.testing.assert_allclose(b["power"], a["power"], rtol=1e-8, atol=1e-10)
+
+
+def check_offbin_target_per_bin(orc=stap):
+    """A target a quarter bin off its Doppler bin, relative taps and per-bin
+    steering: the largest output is at the target's cell and steering vector,
+    within one bin of its Doppler."""
+    wl = synth.with_(synth.SMALL, target_offset=0.25)
+    cube = synth.make_cube(wl)
+    o = orc.run(cube, synth.steering_per_bin(wl), wl.tdof, wl.n_block, wl.load_eps, relative=True)
+    sc = synth.scene(wl)
+    k, s, r = np.unravel_index(int(np.argmax(o["power"])), o["power"].shape)
+    assert (r, s) == (sc.target_cell, sc.target_steer)
+    assert min((k - sc.target_bin) % wl.n_pulse, (sc.target_bin - k) % wl.n_pulse) <= 1
+
+
+# ------------------------------------- training without the cell under test (f1)
+
+def check_training_cells(orc=stap):
+    """Hand-worked cases (R = 64, B = 8, N = 8, G = 2) and the definition's
+    invariants: N distinct cells, none of the block or its guard cells, the
+    nearest ones on each side, half (rounded down) on the left away from the
+    edges."""
+    want = {0: list(range(10, 18)), 3: list(range(18, 22)) + list(range(34, 38)),
+            7: list(range(46, 54)), 1: [2, 3, 4, 5, 18, 19, 20, 21]}
+    for b, cells in want.items():
+        assert list(orc.training_cells(64, 8, b, 2)) == cells, b
+    for R, B, G in ((64, 8, 0), (96, 12, 3), (512, 32, 4), (40, 5, 1), (30, 3, 5)):
+        N = R // B
+        for b in range(B):
+            cells = orc.training_cells(R, B, b, G)
+            assert len(cells) == N and len(set(cells.tolist())) == N
+            assert cells.min() >= 0 and cells.max() < R
+            assert not np.any((cells >= b * N - G) & (cells < b * N + N + G))
+            left, right = cells[cells < b * N], cells[cells >= b * N]
+            if len(left):
+                assert left.max() == b * N - G - 1 and np.all(np.diff(left) == 1)
+            if len(right):
+                assert right.min() == b * N + N + G and np.all(np.diff(right) == 1)
+            if b * N - G >= N // 2 and R - (b * N + N + G) >= N - N // 2:
+                assert len(left) == N // 2
+    with pytest.raises(ValueError):
+        orc.training_cells(30, 3, 1, 6)
+
+
+def check_covariance_excluded_brute_force(orc=stap):
+    P, D, R, B, G = 2, 3, 24, 4, 2
+    X = _crandn(_rng(12), P, D, R)
+    Rh = orc.covariance(X, B, guard=G)
+    N = R // B
+    for b in range(B):
+        cells = [r for r in range(R) if not (b * N - G <= r < b * N + N + G)]
+        cells.sort(key=lambda r: (abs(r - (b * N + N / 2 - 0.5)), r))
+        train = orc.training_cells(R, B, b, G)
+        for k in range(P):
+            acc = np.zeros((D, D), complex)
+            for r in train:
+                acc += np.outer(X[k, :, r], np.conj(X[k, :, r]))
+            np.testing.assert_allclose(Rh[k, b], acc / N, atol=1e-13)
+
+
+def check_excluded_cut_no_self_nulling(orc=stap):
+    """With its own cells in the training set a target nulls itself: its AMF
+    power is bounded by x^H R_L^-1 x < N.  Excluding the block and its guard
+    cells, the covariance no longer depends on the target's snapshot, so its
+    power is the closed form |v^H R^-1 x_t|^2 / (v^H R^-1 v) with R built from
+    the training cells alone, it grows as |alpha|^2 when the target's cube
+    column is scaled by alpha (2 here, exact in complex64), and it exceeds N."""
+    wl = synth.SMALL
+    G = 2
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    sc = synth.scene(wl)
+    k, s, r = sc.target_bin, sc.target_steer, sc.target_cell
+    N = wl.n_cell
+    b = r // N
+    inc = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps)
+    exc = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps, guard=G)
+    assert inc["power"][k, s, r] < N < exc["power"][k, s, r]
+    # closed form from the training cells alone (snapshots by the pinned DFT)
+    X = exc["X"]
+    train = orc.training_cells(wl.n_range, wl.n_block, b, G)
+    Rh = sum(np.outer(X[k, :, c], np.conj(X[k, :, c])) for c in train) / N
+    Rl = Rh + wl.load_eps * np.real(np.trace(Rh)) / wl.dof * np.eye(wl.dof)
+    v = V[s].astype(np.complex128)
+    ri_x = np.linalg.solve(Rl, X[k, :, r])
+    ri_v = np.linalg.solve(Rl, v)
+    want = abs(np.vdot(v, ri_x)) ** 2 / np.real(np.vdot(v, ri_v))
+    assert abs(exc["power"][k, s, r] - want) < 1e-9 * want
+    cube2 = cube.copy()
+    cube2[:, :, r] *= 2.0  # exact in complex64
+    exc2 = orc.run(cube2, V, wl.tdof, wl.n_block, wl.load_eps, guard=G)
+    assert abs(exc2["power"][k, s, r] - 4.0 * exc["power"][k, s, r]) < 1e-9 * exc2["power"][k, s, r]
+
+
+def check_run_block_matches_excluded(orc=stap):
+    """The sampled single-block chain with explicit training cells equals the
+    full excluded-training chain."""
+    wl = synth.with_(synth.SMALL, n_range=256, n_block=16)
+    G = 3
+    cube = synth.make_cube(wl)
+    V = synth.steering(wl)
+    o = orc.run(cube, V, wl.tdof, wl.n_block, wl.load_eps, guard=G)
+    N = wl.n_cell
+    for b in (0, 5, wl.n_block - 1):
+        cells = orc.training_cells(wl.n_range, wl.n_block, b, G)
+        ob = orc.run_block(cube[:, :, b * N:(b + 1) * N], V, wl.tdof, wl.load_eps, bins=np.array([1, 9]),
+                           train_block=cube[:, :, cells])
+        np.testing.assert_allclose(ob["W"][:, 0], o["W"][[1, 9], b], rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(ob["power"], o["power"][[1, 9]][:, :, b * N:(b + 1) * N], rtol=1e-9,
+                                   atol=1e-12)
+
+
+METRIC_CHECKS = [check_rel_err_known_norms, check_per_system_rel_err_block_diagonal,
+                 check_sinr_closed_form, check_sinr_loss_closed_form]
+
+
 CHECKS = [check_window_library_and_sums, check_doppler_brute_force, check_doppler_tone,
           check_doppler_impulse, check_parseval, check_covariance_brute_force,
           check_covariance_invariants, check_loading_closed_form,
-          check_solve_library_and_backward, check_white_snapshots, check_info_indefinite]
+          check_solve_library_and_backward, check_white_snapshots, check_info_indefinite,
+          check_doppler_relative_brute_force, check_relative_chain_equivalence,
+          check_offbin_target_per_bin, check_training_cells, check_covariance_excluded_brute_force,
+          check_excluded_cut_no_self_nulling, check_run_block_matches_excluded]
 CHAIN_CHECKS = [check_block_sum_and_cell_bound, check_target_recovered, check_sinr_loss,
                 check_block_sampling]
 
 
 @pytest.mark.parametrize("check", CHECKS, ids=lambda f: f.__name__)
 def test_pin(check):
+    check()
+
+
+@pytest.mark.parametrize("check", METRIC_CHECKS, ids=lambda f: f.__name__)
+def test_metric_pin(check):
     check()
 
 
