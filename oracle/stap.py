@@ -21,6 +21,9 @@ STAP.  The figure's code is not reproduced in the paper's text, so the steps
 below follow textbook post-Doppler STAP with time-staggered DOF.  Readings the
 paper leaves open, each chosen once and used on both sides:
 
+* Subarrays (optional): the C elements are summed in contiguous groups of
+  n_sub into C / n_sub channels before the Doppler step (the reading used
+  for the paper's 1000-channel cube, Sec. 5.3).
 * Doppler: T taps; tap t applies a symmetric Hann window of length
   L = P - T + 1 placed at pulses t .. t+L-1, then a length-P DFT with kernel
   exp(-j 2 pi k p / P), unnormalised, bins in natural order; DOF index
@@ -51,6 +54,25 @@ def hann(L: int) -> np.ndarray:
     """Symmetric Hann window h[n] = 1/2 - 1/2 cos(2 pi n / (L-1)), n = 0..L-1."""
     n = np.arange(L, dtype=np.float64)
     return 0.5 - 0.5 * np.cos(2.0 * np.pi * n / (L - 1))
+
+
+def subarray(cube: np.ndarray, n_sub: int) -> np.ndarray:
+    """Subarray channels: x'[c'][p][r] = sum_{e < n_sub} x[c' n_sub + e][p][r].
+
+    The paper's datacube has 1000 channels (Sec. 5.3); full element-space
+    DOF at that size is far beyond a per-(bin, block) solve, so the elements
+    are first summed in contiguous groups of n_sub (uniform subarrays, the
+    usual reduced-dimension front end), giving C / n_sub channels that the
+    Doppler step then treats as its channels.  n_sub = 1 is the identity.
+    """
+    C, P, R = cube.shape
+    if C % n_sub:
+        raise ValueError("channels must be a multiple of the subarray size")
+    x = cube.astype(np.complex128)
+    out = np.zeros((C // n_sub, P, R), np.complex128)
+    for e in range(n_sub):
+        out += x[e::n_sub]
+    return out
 
 
 def tap_windows(P: int, T: int) -> np.ndarray:
@@ -209,10 +231,12 @@ def inner_products(W: np.ndarray, X: np.ndarray, n_block: int):
 
 
 def run(cube: np.ndarray, V: np.ndarray, T: int, n_block: int, eps: float,
-        keep: bool = True, relative: bool = False, guard: Optional[int] = None) -> Dict[str, np.ndarray]:
+        keep: bool = True, relative: bool = False, guard: Optional[int] = None,
+        n_sub: int = 1) -> Dict[str, np.ndarray]:
     """The whole chain on one cube ``[C][P][R]`` with steering set ``[S][D]``
-    (or ``[P][S][D]`` per bin)."""
-    X = doppler(cube, T, relative)
+    (or ``[P][S][D]`` per bin); with ``n_sub`` > 1 the elements are first
+    summed into C / n_sub subarray channels."""
+    X = doppler(cube if n_sub == 1 else subarray(cube, n_sub), T, relative)
     R_hat = covariance(X, n_block, guard)
     delta, R_L = loading(R_hat, eps)
     W, gamma, info = solve_weights(R_L, V)
@@ -225,7 +249,7 @@ def run(cube: np.ndarray, V: np.ndarray, T: int, n_block: int, eps: float,
 
 def run_block(cube_block: np.ndarray, V: np.ndarray, T: int, eps: float,
               bins: Optional[np.ndarray] = None, relative: bool = False,
-              train_block: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+              train_block: Optional[np.ndarray] = None, n_sub: int = 1) -> Dict[str, np.ndarray]:
     """The chain for ONE training block: ``cube_block`` is ``[C][P][N]``.
 
     Doppler filtering acts on each (channel, range cell) column alone, so the
@@ -233,8 +257,12 @@ def run_block(cube_block: np.ndarray, V: np.ndarray, T: int, eps: float,
     ``train_block`` (``[C][P][N]``, the cube at the block's training cells,
     e.g. ``training_cells``) trains the covariance instead of the block
     itself.  V is ``[S][D]`` or ``[P][S][D]``.  Returns arrays indexed [k][...]
-    over the selected bins with B = 1.
+    over the selected bins with B = 1.  ``n_sub`` > 1 sums the elements into
+    subarray channels first.
     """
+    if n_sub > 1:
+        cube_block = subarray(cube_block, n_sub)
+        train_block = None if train_block is None else subarray(train_block, n_sub)
     X = doppler(cube_block, T, relative)
     Xt = None if train_block is None else doppler(train_block, T, relative)
     if bins is not None:

@@ -57,10 +57,16 @@ class Workload:
     seed: int = 1000
     cube_index: int = 0
     target_offset: float = 0.0   # target Doppler off its bin, in bins (0 = on-bin)
+    n_sub: int = 1               # array elements per subarray channel (1 = none)
+
+    @property
+    def channels(self) -> int:
+        """Channels the processing sees: subarrays of n_sub elements."""
+        return self.n_chan // self.n_sub
 
     @property
     def dof(self) -> int:
-        return self.tdof * self.n_chan
+        return self.tdof * self.channels
 
     @property
     def n_cell(self) -> int:
@@ -86,7 +92,12 @@ MEDIUM = Workload("c16-p128-r4096-d48", 16, 128, 4096, 3, 64, 16, cnr_db=30.0, s
 LARGE = Workload("c32-p256-r16384-d96", 32, 256, 16384, 3, 128, 32, cnr_db=40.0, seed=1002)
 XLARGE = Workload("c64-p512-r32768-d192", 64, 512, 32768, 3, 256, 64, cnr_db=40.0, seed=1004)
 
-WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, XLARGE)}
+# The paper's STAP cube (Sec. 5.3): 100 pulses x 1000 channels x 30000
+# samples per pulse, the 1000 elements summed into 20 subarrays of 50; T = 3
+# gives D = 60, and 250 training blocks of 120 cells = 2 D each.
+PAPER = Workload("c1000s50-p100-r30000-d60", 1000, 100, 30000, 3, 250, 32, cnr_db=40.0, seed=1005, n_sub=50)
+
+WORKLOADS = {w.name: w for w in (SMALL, MEDIUM, LARGE, XLARGE, PAPER)}
 
 
 def uneven_batch(count: int = 64, seed: int = 1003) -> List[Workload]:
@@ -184,10 +195,18 @@ def steering(wl: Workload) -> np.ndarray:
 
     A uniform linear array at half-wavelength spacing; the temporal part is one
     for every tap, matching on-bin targets with the window of tap t placed at
-    pulses t .. t+L-1.
+    pulses t .. t+L-1.  With subarrays of n elements the channel response is
+    that of its elements, v_s[t*C' + c'] = sum_{e < n} exp(j 2 pi theta_s
+    (c' n + e)), the array's own response to a plane wave from theta_s.
     """
     th = steer_theta(wl.n_steer)
-    spatial = np.exp(2j * np.pi * th[:, None] * np.arange(wl.n_chan)[None, :])
+    n = wl.n_sub
+    spatial = np.exp(2j * np.pi * th[:, None] * n * np.arange(wl.channels)[None, :])   # [S][C/n]
+    if n > 1:
+        # array factor of n elements: exp(j pi theta (n-1)) sin(pi theta n) / sin(pi theta)
+        s = np.sin(np.pi * th)
+        af = np.where(np.abs(s) > 1e-12, np.sin(np.pi * th * n) / np.where(s == 0, 1.0, s), float(n))
+        spatial = spatial * (np.exp(1j * np.pi * th * (n - 1)) * af)[:, None]
     return np.tile(spatial, (1, wl.tdof)).astype(np.complex64)
 
 
@@ -198,10 +217,10 @@ def steering_per_bin(wl: Workload) -> np.ndarray:
     the temporal phase exp(j 2 pi k t / P) across the taps.
     """
     P, T = wl.n_pulse, wl.tdof
-    spatial = steering(wl)[:, :wl.n_chan].astype(np.complex128)          # [S][C]
+    spatial = steering(wl)[:, :wl.channels].astype(np.complex128)        # [S][C]
     ramp = np.exp(2j * np.pi * np.outer(np.arange(P), np.arange(T)) / P)  # [P][T]
     V = ramp[:, None, :, None] * spatial[None, :, None, :]               # [P][S][T][C]
-    return V.reshape(P, wl.n_steer, T * wl.n_chan).astype(np.complex64)
+    return V.reshape(P, wl.n_steer, T * wl.channels).astype(np.complex64)
 
 
 def with_(wl: Workload, **kw) -> Workload:

@@ -490,6 +490,63 @@ def check_run_block_matches_excluded(orc=stap):
                                    atol=1e-12)
 
 
+def check_subarray_brute_force(orc=stap):
+    """Subarray channels by explicit loops: channel c' sums elements
+    c' n .. c' n + n - 1; n = 1 is the identity."""
+    rng = _rng(21)
+    x = _crandn(rng, 12, 5, 3)
+    for n in (1, 2, 3, 4, 6, 12):
+        y = orc.subarray(x, n)
+        assert y.shape == (12 // n, 5, 3)
+        for c in range(12 // n):
+            for p in range(5):
+                for r in range(3):
+                    acc = 0j
+                    for e in range(n):
+                        acc += x[c * n + e, p, r]
+                    assert abs(y[c, p, r] - acc) < 1e-12
+    with pytest.raises(ValueError):
+        orc.subarray(x, 5)
+
+
+def check_subarray_plane_wave(orc=stap):
+    """A plane wave exp(j 2 pi theta c) over the elements gives subarray c'
+    the closed form exp(j 2 pi theta c' n) (1 - exp(j 2 pi theta n)) /
+    (1 - exp(j 2 pi theta)): the phase centre steps by n elements and the
+    magnitude is the array factor of n elements."""
+    C, n = 40, 8
+    for theta in (0.013, -0.21, 0.37):
+        x = np.exp(2j * np.pi * theta * np.arange(C))[:, None, None] * np.ones((1, 2, 2))
+        y = orc.subarray(x, n)
+        geo = (1 - cmath.exp(2j * math.pi * theta * n)) / (1 - cmath.exp(2j * math.pi * theta))
+        for c in range(C // n):
+            want = cmath.exp(2j * math.pi * theta * c * n) * geo
+            assert np.all(np.abs(y[c] - want) < 1e-12)
+
+
+def check_doppler_p100(orc=stap):
+    """The paper's pulse count P = 100 (not a power of two): brute-force DFT
+    of every tap, and the on-bin tone giving sum h = (L - 1) / 2 = 48.5 in
+    every tap (L = 98)."""
+    C, P, R, T = 1, 100, 2, 3
+    rng = _rng(3)
+    x = _crandn(rng, C, P, R)
+    L = P - T + 1
+    h = np.hanning(L)
+    X = orc.doppler(x, T)
+    for k in (0, 1, 37, 50, 99):
+        for t in range(T):
+            for r in range(R):
+                acc = 0j
+                for p in range(t, t + L):
+                    acc += h[p - t] * x[0, p, r] * cmath.exp(-2j * math.pi * k * p / P)
+                assert abs(X[k, t, r] - acc) < 1e-11
+    for k0 in (3, 50, 71):
+        tone = np.exp(2j * np.pi * k0 * np.arange(P) / P)[None, :, None] * np.ones((2, 1, 1))
+        Xt = orc.doppler(tone, T)
+        assert np.all(np.abs(Xt[k0] - 48.5) < 1e-10)
+
+
 METRIC_CHECKS = [check_rel_err_known_norms, check_per_system_rel_err_block_diagonal,
                  check_sinr_closed_form, check_sinr_loss_closed_form]
 
@@ -500,7 +557,8 @@ CHECKS = [check_window_library_and_sums, check_doppler_brute_force, check_dopple
           check_solve_library_and_backward, check_white_snapshots, check_info_indefinite,
           check_doppler_relative_brute_force, check_relative_chain_equivalence,
           check_offbin_target_per_bin, check_training_cells, check_covariance_excluded_brute_force,
-          check_excluded_cut_no_self_nulling, check_run_block_matches_excluded]
+          check_excluded_cut_no_self_nulling, check_run_block_matches_excluded,
+          check_subarray_brute_force, check_subarray_plane_wave, check_doppler_p100]
 CHAIN_CHECKS = [check_block_sum_and_cell_bound, check_target_recovered, check_sinr_loss,
                 check_block_sampling]
 

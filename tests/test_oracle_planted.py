@@ -138,6 +138,23 @@ def solve_weights(R_L, V):
         V = V[0]
     return _orig_sw(R_L, V)
 """,
+    "subarray_interleaved": """
+def subarray(cube, n_sub):
+    C, P, R = cube.shape
+    if C % n_sub:
+        raise ValueError("channels must be a multiple of the subarray size")
+    x = cube.astype(np.complex128)
+    m = C // n_sub
+    return np.stack([x[c::m].sum(axis=0) for c in range(m)])
+""",
+    "subarray_mean": """
+def subarray(cube, n_sub):
+    C, P, R = cube.shape
+    if C % n_sub:
+        raise ValueError("channels must be a multiple of the subarray size")
+    x = cube.astype(np.complex128)
+    return x.reshape(C // n_sub, n_sub, P, R).mean(axis=1)
+""",
 }
 
 
