@@ -15,12 +15,17 @@
  *
  *   Doppler    X[k][t*C+c][r] = sum_p h_t[p] x[c][p][r] exp(-j 2 pi k p / P),
  *              h_t[p] = h[p-t] for t <= p < t+L, L = P-T+1, h the symmetric
- *              Hann window h[n] = 1/2 - 1/2 cos(2 pi n/(L-1)); k = 0..P-1.
- *   Covariance R_hat[k][b] = (1/N) sum_{r in block b} X[k][:,r] X[k][:,r]^H,
- *              blocks of N = R/B contiguous range cells.
+ *              Hann window h[n] = 1/2 - 1/2 cos(2 pi n/(L-1)); k = 0..P-1
+ *              (with STAP_TAP_RELATIVE the kernel is exp(-j 2 pi k (p-t)/P)).
+ *   Covariance R_hat[k][b] = (1/N) sum_{r in Omega_b} X[k][:,r] X[k][:,r]^H,
+ *              Omega_b the N cells of block b (blocks of N = R/B
+ *              contiguous range cells), or with STAP_TRAIN_EXCLUDE the N
+ *              nearest cells outside the block and its guard cells.
  *   Loading    delta = eps * Re tr(R_hat) / D,  R_L = R_hat + delta I.
  *   Weights    R_L = L L^H (Cholesky),  u_s = R_L^-1 v_s,
- *              gamma_s = Re(v_s^H u_s),  w_s = u_s / sqrt(gamma_s).
+ *              gamma_s = Re(v_s^H u_s),  w_s = u_s / sqrt(gamma_s); the
+ *              steering vectors v_s are shared by every bin, or given per
+ *              bin (steer_per_bin).
  *   Output     y[k][s][r] = w_{k,b(r),s}^H X[k][:,r],  power = |y|^2.
  *
  * Conventions for every entry point:
@@ -41,8 +46,14 @@
  *     0 = success, j > 0 = 1-based index of the first bad pivot); that
  *     system's weights and output power are zero and the call still returns
  *     STAP_OK.
- *   - Limits: n_pulse P a power of two in [32, 512]; 1 <= tdof T <= 4 and
- *     T < P; D = T*C <= 192; n_range R divisible by n_block B; 1 <= S <= 64.
+ *   - Limits: n_pulse P a power of two in [32, 512] or 100 (the paper's
+ *     pulse count); 1 <= tdof T <= 4 and T < P; D = T*C <= 192 with C the
+ *     channels after subarray summing; n_range R divisible by n_block B;
+ *     1 <= S <= 64.
+ *   - Subarrays (the reading used for the paper's 1000-channel cube, Sec.
+ *     5.3): with subarray = n > 1 the cube holds n_chan array elements and
+ *     channel c is the sum of elements c*n .. c*n + n - 1, formed by the
+ *     Doppler step as it reads the cube.
  */
 #ifndef STAP_H
 #define STAP_H
@@ -81,6 +92,31 @@ typedef enum stap_precision {
   STAP_PREC_FP8 = 2
 } stap_precision;
 
+/* Which range cells train the covariance of block b (cells [bN, bN+N)). */
+typedef enum stap_training {
+  /* The block's own N cells (the cells under test are part of their own
+   * training set). */
+  STAP_TRAIN_BLOCK = 0,
+  /* Standard STAP practice (Melvin 2014): the block and `guard_cells` cells
+   * on each side are excluded, and the N nearest remaining cells train the
+   * block -- floor(N/2) on the left and the rest on the right, moved to the
+   * other side where a side runs out of cells at the edge of the cube.
+   * Every block must find N such cells: R - N - 2G >= N for interior
+   * blocks, R - N - G >= N at the edges (STAP_ERR_SHAPE otherwise). */
+  STAP_TRAIN_EXCLUDE = 1
+} stap_training;
+
+/* Phase reference of the time-staggered taps in the Doppler DFT. */
+typedef enum stap_tap_phase {
+  /* Absolute pulse index: tap t's DFT kernel is exp(-j 2 pi k p / P) at
+   * pulse p, so an on-bin target has the same phase in every tap. */
+  STAP_TAP_ABSOLUTE = 0,
+  /* Each tap referenced to its own first pulse: exp(-j 2 pi k (p - t) / P),
+   * the DFT of the windowed sub-CPI itself; an on-bin target at bin k then
+   * carries exp(j 2 pi k t / P) in tap t, which per-bin steering matches. */
+  STAP_TAP_RELATIVE = 1
+} stap_tap_phase;
+
 /* One datacube's problem statement (Sec. 5.3: pulses x channels x samples),
  * plus the adaptive-processing parameters. */
 typedef struct stap_problem {
@@ -93,15 +129,25 @@ typedef struct stap_problem {
   float load_eps;        /* eps >= 0: loading delta = eps * tr(R_hat) / D */
   int32_t precision;     /* stap_precision */
   int32_t refine_steps;  /* FP64 iterative-refinement steps, 0..4 */
-  int32_t reserved;      /* must be 0 */
+  int32_t training;      /* stap_training */
   int64_t cube_stride_chan;   /* elements between channels of `cube`; 0 = P*R */
   int64_t cube_stride_pulse;  /* elements between pulses of `cube`; 0 = R.
                                  The range stride is always 1. */
+  int32_t guard_cells;   /* G >= 0 guard cells per side (STAP_TRAIN_EXCLUDE;
+                            must be 0 with STAP_TRAIN_BLOCK) */
+  int32_t tap_phase;     /* stap_tap_phase */
+  int32_t steer_per_bin; /* 0: one steering set V[S][D] for every Doppler
+                            bin; 1: a set per bin, V[P][S][D] */
+  int32_t subarray;      /* array elements summed into each channel: n_chan
+                            counts elements, the processing sees
+                            C = n_chan / subarray channels (0 or 1: none) */
 } stap_problem;
 
 /* Doppler filtering with time-staggered DOF (statements S and T of the
  * paper's kernel, Sec. 4.2; Table 2 row fft_{2D,axis=1}).
- *   cube  in : x[C][P][R] complex, strides from `prob` (range stride 1).
+ *   cube  in : x[n_chan][P][R] complex, strides from `prob` (range stride
+ *              1; channels outermost, or pulses outermost as in the paper's
+ *              pulses x channels x samples cube).
  *   snap  out: X[P][D][R] complex, D = T*C, d = t*C + c, bins k = 0..P-1.
  * FP32 arithmetic for every precision. */
 stap_status stap_doppler(const stap_problem* prob, const stap_cf32* cube,
@@ -120,7 +166,7 @@ stap_status stap_covariance(const stap_problem* prob, const stap_cf32* snap,
 
 /* Adaptive weights by Cholesky solves (the textbook STAP weight solve).
  *   cov   in : R_L[P][B][D][D] Hermitian; only the lower triangle is read.
- *   steer in : V[S][D] steering vectors.
+ *   steer in : V[S][D] steering vectors, or V[P][S][D] with steer_per_bin.
  *   w     out: W[P][B][S][D], w_s = R_L^-1 v_s / sqrt(v_s^H R_L^-1 v_s).
  *   info  out: info[P][B] int32 (0 = ok, j = first non-positive pivot).
  * FP32 factorisation and triangular solves; prob->refine_steps steps of
@@ -133,7 +179,7 @@ stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov,
  * stap_run takes): the loaded covariance stays on chip.  Same definitions,
  * arithmetic and outputs as stap_covariance followed by stap_solve_weights
  * (weights and info; the covariance itself is not written).
- *   snap  in : X[P][D][R];  steer in: V[S][D].
+ *   snap  in : X[P][D][R];  steer in: V[S][D] (V[P][S][D] with steer_per_bin).
  *   w     out: W[P][B][S][D];  info out: info[P][B].
  * STAP_ERR_UNSUPPORTED for D > 128 or FP8 (use the two stage calls). */
 stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap,
@@ -153,7 +199,7 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
  * independent cubes of possibly different shapes, enqueued as one batch
  * (the paper's fused parallel loop over independent units, Sec. 4.2).
  *   cubes[i]   in : x_i as for stap_doppler.
- *   steers[i]  in : V_i[S_i][D_i].
+ *   steers[i]  in : V_i[S_i][D_i] (V_i[P_i][S_i][D_i] with steer_per_bin).
  *   powers[i]  out: power_i[P_i][S_i][R_i].
  *   weights    out: NULL, or weights[i] = W_i[P_i][B_i][S_i][D_i] (each may be
  *                   NULL).
@@ -175,6 +221,32 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs,
                      const stap_cf32* const* steers, float* const* powers,
                      stap_cf32* const* weights, int32_t* const* info,
                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Cell-averaging CFAR parameters (detection on the output power). */
+typedef struct stap_cfar_params {
+  int32_t n_ref;    /* reference cells per side, 1..64 */
+  int32_t n_guard;  /* guard cells per side between the cell and its
+                       reference cells, 0..64 */
+  double alpha;     /* threshold factor > 0; for N = 2 n_ref reference cells
+                       of exponential noise, alpha = N (Pfa^(-1/N) - 1) gives
+                       false-alarm probability Pfa */
+} stap_cfar_params;
+
+/* Cell-averaging CFAR detection along range on the output power (the
+ * textbook CA-CFAR detector, Finn and Johnson 1968, applied to each
+ * (Doppler bin, steering vector) row; the step after the paper's kernel).
+ * For cell r the reference cells are r-g-n .. r-g-1 and r+g+1 .. r+g+n
+ * (n = n_ref, g = n_guard); cells outside [0, R) are left out and n_used
+ * counts the rest.  The reference cells are added in FP64 one at a time in
+ * that order and the cell is a detection when
+ *   (double) power[r] * n_used  >  alpha * sum
+ * (FP64, no fused multiply-add), so the mask is reproducible bit for bit.
+ *   power  in : power[P][S][R] float as written by stap_run or
+ *               stap_inner_products (only P, S and R of prob are used).
+ *   detect out: detect[P][S][R] uint8, 1 = detection, 0 = none.
+ * STAP_ERR_ARG for a null pointer or parameters out of range. */
+stap_status stap_cfar(const stap_problem* prob, const stap_cfar_params* cfar,
+                      const float* power, uint8_t* detect, void* stream);
 
 /* Kernel-variant selection, written by the autotuner (tune.py) and read by
  * stap_run and stap_covariance_solve (kind 0, the fused covariance->solve

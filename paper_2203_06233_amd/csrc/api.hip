@@ -20,34 +20,57 @@ namespace {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-bool pow2_pulse(int p) {
-  return p == 32 || p == 64 || p == 128 || p == 256 || p == 512;
+// Pulse counts with a Doppler kernel: the powers of two 32..512 and the
+// paper's 100.
+bool valid_pulse(int p) {
+  return p == 32 || p == 64 || p == 100 || p == 128 || p == 256 || p == 512;
 }
+// Array elements per processing channel (0 and 1 both mean none).
+int sub_of(const stap_problem* q) { return q->subarray > 1 ? q->subarray : 1; }
 
 stap_status check(const stap_problem* q) {
   if (!q) return STAP_ERR_ARG;
-  if (q->reserved != 0) return STAP_ERR_ARG;
+  if (q->subarray < 0) return STAP_ERR_ARG;
+  if (q->training != STAP_TRAIN_BLOCK && q->training != STAP_TRAIN_EXCLUDE) return STAP_ERR_ARG;
+  if (q->guard_cells < 0 || (q->training == STAP_TRAIN_BLOCK && q->guard_cells != 0)) return STAP_ERR_ARG;
+  if (q->tap_phase != STAP_TAP_ABSOLUTE && q->tap_phase != STAP_TAP_RELATIVE) return STAP_ERR_ARG;
+  if (q->steer_per_bin != 0 && q->steer_per_bin != 1) return STAP_ERR_ARG;
   if (!(q->load_eps >= 0.f) || !isfinite(q->load_eps)) return STAP_ERR_ARG;
   if (q->precision < STAP_PREC_FP32 || q->precision > STAP_PREC_FP8) return STAP_ERR_ARG;
   if (q->refine_steps < 0 || q->refine_steps > 4) return STAP_ERR_ARG;
   if (q->n_chan < 1 || q->n_range < 1 || q->n_block < 1 || q->n_steer < 1 || q->tdof < 1)
     return STAP_ERR_SHAPE;
-  if (!pow2_pulse(q->n_pulse)) return STAP_ERR_SHAPE;
+  if (!valid_pulse(q->n_pulse)) return STAP_ERR_SHAPE;
   if (q->tdof > stap::kMaxTdof || q->tdof >= q->n_pulse) return STAP_ERR_SHAPE;
-  if ((long long)q->tdof * q->n_chan > stap::kMaxDof) return STAP_ERR_SHAPE;
+  if (q->n_chan % sub_of(q) != 0) return STAP_ERR_SHAPE;
+  if ((long long)q->tdof * (q->n_chan / sub_of(q)) > stap::kMaxDof) return STAP_ERR_SHAPE;
   if (q->n_steer > stap::kMaxSteer) return STAP_ERR_SHAPE;
   if (q->n_range % q->n_block != 0) return STAP_ERR_SHAPE;
   if ((long long)q->n_pulse * q->n_block > 0x7fffffffLL) return STAP_ERR_SHAPE;
+  // The range rows of the cube must not overlap: channels outermost
+  // ([C][P][R], the default) or pulses outermost ([P][C][R], the paper's
+  // pulses x channels x samples), each with rows of at least R elements.
   const long long sp = q->cube_stride_pulse ? q->cube_stride_pulse : q->n_range;
   const long long sc = q->cube_stride_chan ? q->cube_stride_chan : (long long)q->n_pulse * sp;
-  if (sp < q->n_range || sc < 0) return STAP_ERR_SHAPE;
-  if (q->n_chan > 1 && sc < (long long)(q->n_pulse - 1) * sp + q->n_range) return STAP_ERR_SHAPE;
+  const bool chan_outer = sp >= q->n_range && (q->n_chan == 1 || sc >= (long long)(q->n_pulse - 1) * sp + q->n_range);
+  const bool pulse_outer = sc >= q->n_range && sp >= (long long)(q->n_chan - 1) * sc + q->n_range;
+  if (!chan_outer && !pulse_outer) return STAP_ERR_SHAPE;
+  if (q->training == STAP_TRAIN_EXCLUDE) {
+    // every block needs N training cells outside itself and its guard cells
+    const long long N = q->n_range / q->n_block;
+    for (long long b = 0; b < q->n_block; ++b) {
+      const long long lo = b * N - q->guard_cells, hi = b * N + N + q->guard_cells;
+      const long long avail = (lo > 0 ? lo : 0) + (q->n_range - hi > 0 ? q->n_range - hi : 0);
+      if (avail < N) return STAP_ERR_SHAPE;
+    }
+  }
   return STAP_OK;
 }
 
 Dims dims_of(const stap_problem* q) {
   Dims d;
-  d.C = q->n_chan;
+  d.sub = sub_of(q);
+  d.C = q->n_chan / d.sub;
   d.P = q->n_pulse;
   d.R = q->n_range;
   d.T = q->tdof;
@@ -61,13 +84,17 @@ Dims dims_of(const stap_problem* q) {
   d.refine = q->refine_steps;
   d.sp = q->cube_stride_pulse ? q->cube_stride_pulse : d.R;
   d.sc = q->cube_stride_chan ? q->cube_stride_chan : (long long)d.P * d.sp;
+  d.train = q->training;
+  d.guard = q->guard_cells;
+  d.tap_rel = q->tap_phase;
+  d.steer_bin = q->steer_per_bin;
   return d;
 }
 
 // Every validated shape is solvable: D <= 128 on a 16 x 16 thread grid,
 // D <= 192 on a 32 x 16 grid.
 stap_status check_solvable(const stap_problem* q) {
-  return (q->tdof * q->n_chan > stap::kMaxDof) ? STAP_ERR_UNSUPPORTED : STAP_OK;
+  return (q->tdof * (q->n_chan / sub_of(q)) > stap::kMaxDof) ? STAP_ERR_UNSUPPORTED : STAP_OK;
 }
 
 stap_status hip_status(hipError_t e) { return e == hipSuccess ? STAP_OK : STAP_ERR_HIP; }
@@ -129,7 +156,7 @@ struct Parts {
   size_t total() const { return snap + cov + delta + w + info; }
 };
 Parts parts_of(const stap_problem* q) {
-  const size_t P = q->n_pulse, D = (size_t)q->tdof * q->n_chan, R = q->n_range, B = q->n_block,
+  const size_t P = q->n_pulse, D = (size_t)q->tdof * (q->n_chan / sub_of(q)), R = q->n_range, B = q->n_block,
                S = q->n_steer;
   const Dims d = dims_of(q);
   const bool fused = stap::fused_supported(d) && !stap::wsolve_supported(d);
@@ -164,82 +191,10 @@ GraphCache& graphs() {
   return *g;
 }
 
-}  // namespace
-
-extern "C" {
-
-stap_status stap_check_problem(const stap_problem* prob) { return check(prob); }
-
-stap_status stap_doppler(const stap_problem* prob, const stap_cf32* cube, stap_cf32* snap, void* stream) {
-  stap_status s = check(prob);
-  if (s != STAP_OK) return s;
-  if (!cube || !snap) return STAP_ERR_ARG;
-  if (!aligned(cube, 8) || !aligned(snap, 8)) return STAP_ERR_ALIGN;
-  const Dims d = dims_of(prob);
-  return hip_status(stap::launch_doppler(d, reinterpret_cast<const float2*>(cube),
-                                         reinterpret_cast<float2*>(snap), (hipStream_t)stream));
-}
-
-stap_status stap_covariance(const stap_problem* prob, const stap_cf32* snap, stap_cf32* cov, float* delta,
-                            void* stream) {
-  stap_status s = check(prob);
-  if (s != STAP_OK) return s;
-  if (!snap || !cov) return STAP_ERR_ARG;
-  if (!aligned(snap, 8) || !aligned(cov, 8) || !aligned(delta, 4)) return STAP_ERR_ALIGN;
-  const Dims d = dims_of(prob);
-  return hip_status(stap::launch_covariance(d, reinterpret_cast<const float2*>(snap),
-                                            reinterpret_cast<float2*>(cov), delta, (hipStream_t)stream));
-}
-
-stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov, const stap_cf32* steer,
-                               stap_cf32* w, int32_t* info, void* stream) {
-  stap_status s = check(prob);
-  if (s != STAP_OK) return s;
-  if (!cov || !steer || !w || !info) return STAP_ERR_ARG;
-  if (!aligned(cov, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
-  if ((s = check_solvable(prob)) != STAP_OK) return s;
-  const Dims d = dims_of(prob);
-  return hip_status(stage_solve(d, reinterpret_cast<const float2*>(cov), reinterpret_cast<const float2*>(steer),
-                                 reinterpret_cast<float2*>(w), info, (hipStream_t)stream));
-}
-
-stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap, const stap_cf32* steer,
-                                  stap_cf32* w, int32_t* info, void* stream) {
-  stap_status s = check(prob);
-  if (s != STAP_OK) return s;
-  if (!snap || !steer || !w || !info) return STAP_ERR_ARG;
-  if (!aligned(snap, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
-  const Dims d = dims_of(prob);
-  if (!stap::fused_supported(d)) return STAP_ERR_UNSUPPORTED;
-  return hip_status(stap::launch_fused(d, reinterpret_cast<const float2*>(snap), reinterpret_cast<const float2*>(steer),
-                                       reinterpret_cast<float2*>(w), info, (hipStream_t)stream, fused_variant(d)));
-}
-
-stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w, const stap_cf32* snap,
-                                float* power, stap_cf32* y, void* stream) {
-  stap_status s = check(prob);
-  if (s != STAP_OK) return s;
-  if (!w || !snap || !power) return STAP_ERR_ARG;
-  if (!aligned(w, 8) || !aligned(snap, 8) || !aligned(power, 4) || !aligned(y, 8)) return STAP_ERR_ALIGN;
-  const Dims d = dims_of(prob);
-  return hip_status(stap::launch_inner(d, reinterpret_cast<const float2*>(w),
-                                       reinterpret_cast<const float2*>(snap), power,
-                                       reinterpret_cast<float2*>(y), (hipStream_t)stream));
-}
-
-size_t stap_workspace_size(const stap_problem* probs, int32_t n_probs) {
-  if (!probs || n_probs < 1) return 0;
-  size_t total = table_bytes(n_probs);
-  for (int i = 0; i < n_probs; ++i) {
-    if (check(&probs[i]) != STAP_OK) return 0;
-    total += parts_of(&probs[i]).total();
-  }
-  return total;
-}
-
-stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
-                     const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
-                     int32_t* const* info, void* workspace, size_t workspace_bytes, void* stream) {
+// Arguments of a stap_run call, checked on the host before any HIP call.
+stap_status check_run(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
+                      const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
+                      int32_t* const* info) {
   if (!probs || n_probs < 1 || !cubes || !steers || !powers) return STAP_ERR_ARG;
   for (int i = 0; i < n_probs; ++i) {
     stap_status s = check(&probs[i]);
@@ -252,12 +207,45 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
     if (weights && !aligned(weights[i], 8)) return STAP_ERR_ALIGN;
     if (info && !aligned(info[i], 4)) return STAP_ERR_ALIGN;
   }
-  const size_t need = stap_workspace_size(probs, n_probs);
-  if (!workspace || workspace_bytes < need) return STAP_ERR_WORKSPACE;
-  if (!aligned(workspace, kAlign)) return STAP_ERR_ALIGN;
+  return STAP_OK;
+}
 
-  hipStream_t st = (hipStream_t)stream;
-  char* const ws0 = static_cast<char*>(workspace);
+// The batched problem table reaches the device as kernel arguments (by
+// value), so a launch recorded into a graph carries its own copy of the
+// table and nothing on the host has to outlive the call.
+constexpr int kTableChunk = 3072 / (int)sizeof(stap::ProbDesc);
+struct TableChunk {
+  int first, n;
+  stap::ProbDesc d[kTableChunk];
+};
+static_assert(sizeof(stap::ProbDesc) % 8 == 0, "table entries are copied as 8-byte words");
+
+__global__ void table_kernel(stap::ProbDesc* __restrict__ table, TableChunk c) {
+  const int words = c.n * (int)(sizeof(stap::ProbDesc) / 8);
+  const unsigned long long* src = reinterpret_cast<const unsigned long long*>(c.d);
+  unsigned long long* dst = reinterpret_cast<unsigned long long*>(table + c.first);
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t upload_table(stap::ProbDesc* table, const std::vector<stap::ProbDesc>& desc, hipStream_t st) {
+  for (int first = 0; first < (int)desc.size(); first += kTableChunk) {
+    TableChunk c;
+    c.first = first;
+    c.n = std::min(kTableChunk, (int)desc.size() - first);
+    for (int i = 0; i < c.n; ++i) c.d[i] = desc[first + i];
+    hipLaunchKernelGGL(table_kernel, dim3(1), dim3(256), 0, st, table, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// stap_run after argument checks: ws0 is a workspace of at least
+// stap_workspace_size() bytes.  `graphs_ok` allows the batched chain to be
+// replayed from the graph cache.
+stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
+                     const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
+                     int32_t* const* info, char* const ws0, hipStream_t st, bool graphs_ok) {
   stap::ProbDesc* table = reinterpret_cast<stap::ProbDesc*>(ws0);
   char* ws = ws0 + table_bytes(n_probs);
   std::vector<stap::ProbDesc> desc(n_probs);
@@ -323,13 +311,9 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
   const int ty = fused_variant(cls);
   const int prec = probs[0].precision, refine = probs[0].refine_steps;
 
-  if (hipMemcpyAsync(table, desc.data(), desc.size() * sizeof(stap::ProbDesc), hipMemcpyHostToDevice, st) !=
-      hipSuccess)
-    return STAP_ERR_HIP;
-
   // Doppler launches, one per pulse count (at most kMaxBatchArg cubes each).
   std::vector<std::pair<stap::BatchIndex, int>> dop;
-  for (int P : {32, 64, 128, 256, 512}) {
+  for (int P : {32, 64, 100, 128, 256, 512}) {
     stap::BatchIndex bi;
     bi.n = 0;
     int tiles = 0;
@@ -361,13 +345,14 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
     return stap::launch_inner_batched(table, n_probs, total, max_dof, max_steer, prec, s);
   };
 
+  if (upload_table(table, desc, st) != hipSuccess) return STAP_ERR_HIP;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) return STAP_ERR_HIP;
-  if (!g_use_graphs || cap != hipStreamCaptureStatusNone) return hip_status(enqueue(st));
+  if (!graphs_ok || !g_use_graphs || cap != hipStreamCaptureStatusNone) return hip_status(enqueue(st));
 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return STAP_ERR_HIP;
-  std::string key = std::to_string(dev) + "|" + std::to_string((uintptr_t)workspace) + "|" +
+  std::string key = std::to_string(dev) + "|" + std::to_string((uintptr_t)ws0) + "|" +
                     std::to_string(prec) + "|" + std::to_string(refine) + "|" + std::to_string(ty);
   for (auto& pd : desc) {
     key += "|" + std::to_string(pd.d.C) + "," + std::to_string(pd.d.P) + "," + std::to_string(pd.d.R) + "," +
@@ -397,6 +382,104 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
     it = gc.exec.emplace(key, ge).first;
   }
   return hip_status(hipGraphLaunch(it->second, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+stap_status stap_check_problem(const stap_problem* prob) { return check(prob); }
+
+stap_status stap_doppler(const stap_problem* prob, const stap_cf32* cube, stap_cf32* snap, void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!cube || !snap) return STAP_ERR_ARG;
+  if (!aligned(cube, 8) || !aligned(snap, 8)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  return hip_status(stap::launch_doppler(d, reinterpret_cast<const float2*>(cube),
+                                         reinterpret_cast<float2*>(snap), (hipStream_t)stream));
+}
+
+stap_status stap_covariance(const stap_problem* prob, const stap_cf32* snap, stap_cf32* cov, float* delta,
+                            void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!snap || !cov) return STAP_ERR_ARG;
+  if (!aligned(snap, 8) || !aligned(cov, 8) || !aligned(delta, 4)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  return hip_status(stap::launch_covariance(d, reinterpret_cast<const float2*>(snap),
+                                            reinterpret_cast<float2*>(cov), delta, (hipStream_t)stream));
+}
+
+stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov, const stap_cf32* steer,
+                               stap_cf32* w, int32_t* info, void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!cov || !steer || !w || !info) return STAP_ERR_ARG;
+  if (!aligned(cov, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
+  if ((s = check_solvable(prob)) != STAP_OK) return s;
+  const Dims d = dims_of(prob);
+  return hip_status(stage_solve(d, reinterpret_cast<const float2*>(cov), reinterpret_cast<const float2*>(steer),
+                                 reinterpret_cast<float2*>(w), info, (hipStream_t)stream));
+}
+
+stap_status stap_covariance_solve(const stap_problem* prob, const stap_cf32* snap, const stap_cf32* steer,
+                                  stap_cf32* w, int32_t* info, void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!snap || !steer || !w || !info) return STAP_ERR_ARG;
+  if (!aligned(snap, 8) || !aligned(steer, 8) || !aligned(w, 8) || !aligned(info, 4)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  if (!stap::fused_supported(d)) return STAP_ERR_UNSUPPORTED;
+  return hip_status(stap::launch_fused(d, reinterpret_cast<const float2*>(snap), reinterpret_cast<const float2*>(steer),
+                                       reinterpret_cast<float2*>(w), info, (hipStream_t)stream, fused_variant(d)));
+}
+
+stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w, const stap_cf32* snap,
+                                float* power, stap_cf32* y, void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!w || !snap || !power) return STAP_ERR_ARG;
+  if (!aligned(w, 8) || !aligned(snap, 8) || !aligned(power, 4) || !aligned(y, 8)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  return hip_status(stap::launch_inner(d, reinterpret_cast<const float2*>(w),
+                                       reinterpret_cast<const float2*>(snap), power,
+                                       reinterpret_cast<float2*>(y), (hipStream_t)stream));
+}
+
+stap_status stap_cfar(const stap_problem* prob, const stap_cfar_params* cfar, const float* power, uint8_t* detect,
+                      void* stream) {
+  stap_status s = check(prob);
+  if (s != STAP_OK) return s;
+  if (!cfar || !power || !detect) return STAP_ERR_ARG;
+  if (cfar->n_ref < 1 || cfar->n_ref > stap::kMaxCfarRef || cfar->n_guard < 0 || cfar->n_guard > stap::kMaxCfarGuard)
+    return STAP_ERR_ARG;
+  if (!(cfar->alpha > 0.0) || !isfinite(cfar->alpha)) return STAP_ERR_ARG;
+  if (!aligned(power, 4)) return STAP_ERR_ALIGN;
+  const Dims d = dims_of(prob);
+  return hip_status(stap::launch_cfar(d, cfar->n_ref, cfar->n_guard, cfar->alpha, power, detect, (hipStream_t)stream));
+}
+
+size_t stap_workspace_size(const stap_problem* probs, int32_t n_probs) {
+  if (!probs || n_probs < 1) return 0;
+  size_t total = table_bytes(n_probs);
+  for (int i = 0; i < n_probs; ++i) {
+    if (check(&probs[i]) != STAP_OK) return 0;
+    total += parts_of(&probs[i]).total();
+  }
+  return total;
+}
+
+stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
+                     const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
+                     int32_t* const* info, void* workspace, size_t workspace_bytes, void* stream) {
+  stap_status s = check_run(probs, n_probs, cubes, steers, powers, weights, info);
+  if (s != STAP_OK) return s;
+  const size_t need = stap_workspace_size(probs, n_probs);
+  if (!workspace || workspace_bytes < need) return STAP_ERR_WORKSPACE;
+  if (!aligned(workspace, kAlign)) return STAP_ERR_ALIGN;
+  return run_impl(probs, n_probs, cubes, steers, powers, weights, info, static_cast<char*>(workspace),
+                  (hipStream_t)stream, true);
 }
 
 void stap_use_graphs(int32_t enable) { g_use_graphs = enable != 0; }

@@ -25,7 +25,7 @@ void bsolve_kernel(const float2* __restrict__ cov,
   using C = BCfg<NSL, NSM, NW>;
   extern __shared__ __align__(16) unsigned char lds[];
   const int sys = blockIdx.x;
-  bsolve_system<C, REFINE>(GlobalRB{cov + (long long)sys * d.D * d.D, d.D}, steer,
+  bsolve_system<C, REFINE>(GlobalRB{cov + (long long)sys * d.D * d.D, d.D}, steer + steer_offset(d, sys),
                            wout + (long long)sys * d.S * d.D, info_out ? info_out + sys : nullptr, d, lds);
 }
 

@@ -14,6 +14,8 @@ constexpr int kMaxSteer = 64;
 constexpr int kMaxTdof = 4;
 constexpr int kMinPulse = 32;
 constexpr int kMaxPulse = 512;
+constexpr int kMaxCfarRef = 64;    // CA-CFAR reference cells per side
+constexpr int kMaxCfarGuard = 64;  // CA-CFAR guard cells per side
 
 // Problem dimensions as the kernels see them (all derived on the host).
 struct Dims {
@@ -24,7 +26,37 @@ struct Dims {
   float eps;
   int prec, refine;
   long long sc, sp;  // cube strides of channel and pulse (elements)
+  int train;         // stap_training
+  int guard;         // guard cells per side (STAP_TRAIN_EXCLUDE)
+  int tap_rel;       // 1: each tap's DFT referenced to its own first pulse
+  int steer_bin;     // 1: steering vectors given per Doppler bin, [P][S][D]
+  int sub;           // array elements summed into each channel C (>= 1)
 };
+
+// The N range cells that train block b, as two runs: cells a0 .. a0+nl-1 and
+// a1 .. a1+(N-nl)-1.  Block mode: the block itself.  Exclude mode: the block
+// and G guard cells per side are skipped; the nearest remaining cells are
+// taken, floor(N/2) on the left and the rest on the right, shifted to the
+// other side where the cube ends (the host has checked that N cells exist).
+struct CellMap {
+  int a0, nl, a1;
+  __host__ __device__ int cell(int c) const { return c < nl ? a0 + c : a1 + (c - nl); }
+};
+__host__ __device__ inline CellMap train_cells(const Dims& d, int b) {
+  if (!d.train) return CellMap{b * d.N, d.N, 0};
+  const int lo = b * d.N - d.guard, hi = b * d.N + d.N + d.guard;
+  const int left = lo > 0 ? lo : 0, right = d.R - hi > 0 ? d.R - hi : 0;
+  const int want_left = d.N / 2 < left ? d.N / 2 : left;
+  const int nr = d.N - want_left < right ? d.N - want_left : right;
+  const int nl = d.N - nr;
+  return CellMap{lo - nl, nl, hi};
+}
+
+// Steering set of system sys (bin sys / B): the shared V[S][D] or the bin's
+// slice of V[P][S][D].
+__host__ __device__ inline long long steer_offset(const Dims& d, long long sys) {
+  return d.steer_bin ? (sys / d.B) * (long long)d.S * d.D : 0;
+}
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -213,6 +245,36 @@ __device__ __forceinline__ void fft_inreg(float2 (&v)[M]) {
       }
     }
   }
+}
+
+// Forward DFT of M points held in registers for M that is not a power of
+// two: v[k] <- sum_n v[n] exp(-2 pi i k n / M), evaluated directly with a
+// correctly rounded compile-time table (M^2 complex products; used for the
+// factors of the 100-pulse transform).
+template <int M>
+__device__ __forceinline__ void dft_inreg(float2 (&v)[M]) {
+  constexpr TwTab<M> tw = make_twtab<M>();
+  float2 out[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    float2 acc = v[0];
+#pragma unroll
+    for (int n = 1; n < M; ++n) {
+      const int m = (k * n) % M;
+      const float c = tw.c[m], sn = -tw.s[m];  // exp(-2 pi i m / M) = c + i sn
+      acc.x = fmaf(v[n].x, c, fmaf(-v[n].y, sn, acc.x));
+      acc.y = fmaf(v[n].x, sn, fmaf(v[n].y, c, acc.y));
+    }
+    out[k] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = out[k];
+}
+
+template <int M>
+__device__ __forceinline__ void dft_any(float2 (&v)[M]) {
+  if constexpr ((M & (M - 1)) == 0) fft_inreg<M>(v);
+  else dft_inreg<M>(v);
 }
 
 // Round-to-nearest-even float -> bf16 bits, and back.

@@ -70,12 +70,13 @@ __device__ __forceinline__ unsigned int f2e4m3(float x) {
 
 // Accumulate R_hat for one system into accR/accI (tile t = wave + NW*i of the
 // lower block triangle, MFMA 16x16 layout: lane l holds rows 4(l/16)+r,
-// column l%16).  X points at the system's first snapshot (row stride
-// rstride).  lds holds Cfg::LDS_BYTES; red holds NW floats.  Returns with the
-// accumulators scaled to R_hat (1/N, FP8 scale undone).
+// column l%16).  X points at row 0, range cell 0 of the system's Doppler bin
+// (row stride rstride); the N training cells are cm.cell(0 .. N-1).  lds
+// holds Cfg::LDS_BYTES; red holds NW floats.  Returns with the accumulators
+// scaled to R_hat (1/N, FP8 scale undone).
 template <class Cfg>
 __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, long long rstride, int D, int N,
-                                               unsigned char* lds, float* red,
+                                               CellMap cm, unsigned char* lds, float* red,
                                                floatx4 (&accR)[Cfg::TPW], floatx4 (&accI)[Cfg::TPW]) {
   constexpr int DP = Cfg::DP, NW = Cfg::NW, MODE = Cfg::MODE, NT = Cfg::NT, TPW = Cfg::TPW;
   constexpr int NTILE = Cfg::NTILE;
@@ -95,7 +96,7 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
     float mx = 0.f;
     for (int e = tid; e < D * N; e += NT) {
       const int row = e / N, cc = e - (e / N) * N;
-      const float2 v = X[(long long)row * rstride + cc];
+      const float2 v = X[(long long)row * rstride + cm.cell(cc)];
       mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
@@ -117,6 +118,10 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
   constexpr int PF = (NE + NT - 1) / NT;
   constexpr int PV = MODE == 1 ? 2 : 1;
   float2 pf[PF][PV];
+  // One run of training cells (the block itself): contiguous loads.  Two
+  // runs (cells under test excluded): each cell through the map.  The test is
+  // uniform over the workgroup.
+  const bool one_run = cm.nl >= N;
   auto load_chunk = [&](int c0) {
     const int nc = min(kCovChunk, N - c0);
 #pragma unroll
@@ -126,16 +131,22 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
         const int row = e / (kCovChunk / 2), cp = e % (kCovChunk / 2);
         float2 v0 = make_float2(0.f, 0.f), v1 = v0;
         if (e < NE && row < D) {
-          const float2* src = X + (long long)row * rstride + c0 + 2 * cp;
-          if (2 * cp < nc) v0 = src[0];
-          if (2 * cp + 1 < nc) v1 = src[1];
+          const float2* xr = X + (long long)row * rstride;
+          if (one_run) {
+            const float2* src = xr + cm.a0 + c0 + 2 * cp;
+            if (2 * cp < nc) v0 = src[0];
+            if (2 * cp + 1 < nc) v1 = src[1];
+          } else {
+            if (2 * cp < nc) v0 = xr[cm.cell(c0 + 2 * cp)];
+            if (2 * cp + 1 < nc) v1 = xr[cm.cell(c0 + 2 * cp + 1)];
+          }
         }
         pf[i][0] = v0;
         pf[i][PV - 1] = v1;
       } else {
         const int row = e / kCovChunk, cc = e % kCovChunk;
         float2 v = make_float2(0.f, 0.f);
-        if (e < NE && row < D && cc < nc) v = X[(long long)row * rstride + c0 + cc];
+        if (e < NE && row < D && cc < nc) v = X[(long long)row * rstride + cm.cell(c0 + cc)];
         pf[i][0] = v;
       }
     }

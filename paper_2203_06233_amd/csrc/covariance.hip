@@ -3,7 +3,10 @@
 // row dot_{2D,2D}):
 //
 //   R_hat = (1/N) X_kb X_kb^H,   delta = eps * Re tr(R_hat) / D,
-//   R_L   = R_hat + delta I.
+//   R_L   = R_hat + delta I,
+//
+// with X_kb the snapshots of bin k at the N training cells of block b (the
+// block itself, or the nearest cells outside it and its guard cells).
 //
 // One workgroup per system; the MFMA work is cov_accumulate() (cov_impl.h).
 // Both triangles are written: the upper is the bitwise conjugate of the
@@ -31,9 +34,9 @@ void cov_kernel(const float2* __restrict__ snap,
   const int sys = blockIdx.x;
   const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
   const int D = d.D;
-  const float2* X = snap + (long long)k * D * d.R + (long long)b * d.N;
+  const float2* X = snap + (long long)k * D * d.R;
   floatx4 accR[Cfg::TPW], accI[Cfg::TPW];
-  cov_accumulate<Cfg>(X, d.R, D, d.N, lds, red, accR, accI);
+  cov_accumulate<Cfg>(X, d.R, D, d.N, train_cells(d, b), lds, red, accR, accI);
   const float dl = cov_delta<Cfg>(accR, D, d.eps, dsum, &s_delta);
   if (delta_out && threadIdx.x == 0) delta_out[sys] = dl;
   float2* out = cov + (long long)sys * D * D;

@@ -3,6 +3,9 @@
 //
 //   X[k][t*C+c][r] = sum_p h[p-t] x[c][p][r] exp(-2 pi i k p / P)
 //
+// or, with each tap referenced to its own first pulse (relative phase),
+// exp(-2 pi i k (p - t) / P), i.e. the absolute form times exp(2 pi i k t / P).
+//
 // One workgroup takes one channel c and RT consecutive range cells.  The
 // length-P DFT is split as P = P1 * P2 (p = P2*n1 + n2, k = k1 + P1*k2):
 //   pass 1  each thread owns one (n2, cell) and keeps the P1 samples
@@ -12,7 +15,10 @@
 //   LDS     one transpose through a [k1][n2][cell] tile;
 //   pass 2  each (k1, cell) runs a P2-point DFT in registers and stores bins
 //           k1 + P1*k2 straight to X[k][d][r] (range fastest, coalesced).
-// The cube is read from HBM once for all T taps.  Twiddles of the inner DFTs
+// The cube is read from HBM once for all T taps; with subarrays, each
+// channel's samples are the sum of its elements, formed as they are loaded.
+// P = 100 (the paper's pulse count) runs the same passes as 10 x 10 with
+// direct in-register DFTs.  Twiddles of the inner DFTs
 // are compile-time constants; the P-point twiddles and the Hann window come
 // from correctly rounded compile-time tables, staged once per workgroup in LDS.
 #include "common.h"
@@ -26,6 +32,12 @@ struct FftShape {
   static constexpr int P1 = 1 << ((LOG + 1) / 2);
   static constexpr int P2 = P / P1;
   static constexpr int RT = 256 / P2;  // range cells per workgroup
+};
+// The paper's 100 pulses: 10 x 10, 25 cells per workgroup (250 of the 256
+// threads take a column in the first pass).
+template <>
+struct FftShape<100> {
+  static constexpr int P1 = 10, P2 = 10, RT = 25;
 };
 
 // One workgroup's tile: channel c, range cells r0 .. r0+RT-1 of one cube.
@@ -47,12 +59,23 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
 
   const int col = tid % RT, n2 = tid / RT;
   const int r = r0 + col;
-  const bool live = r < d.R;
+  const bool live = r < d.R && n2 < P2;
   float2 x[P1];
-  const float2* src = cube + (long long)c * d.sc + r;
 #pragma unroll
-  for (int n1 = 0; n1 < P1; ++n1)
-    x[n1] = live ? src[(long long)(P2 * n1 + n2) * d.sp] : make_float2(0.f, 0.f);
+  for (int n1 = 0; n1 < P1; ++n1) x[n1] = make_float2(0.f, 0.f);
+  if (live) {
+    // channel c is the sum of array elements c*sub .. c*sub + sub - 1 (one
+    // element without subarrays), added in element order
+    for (int e = 0; e < d.sub; ++e) {
+      const float2* src = cube + (long long)(c * d.sub + e) * d.sc + r;
+#pragma unroll
+      for (int n1 = 0; n1 < P1; ++n1) {
+        const float2 v = src[(long long)(P2 * n1 + n2) * d.sp];
+        x[n1].x += v.x;
+        x[n1].y += v.y;
+      }
+    }
+  }
   __syncthreads();
 
   for (int t = 0; t < d.T; ++t) {
@@ -60,14 +83,16 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
 #pragma unroll
     for (int n1 = 0; n1 < P1; ++n1) {
       const int q = P2 * n1 + n2 - t;
-      const float h = (q >= 0) ? hwin[q] : 0.f;
+      const float h = (q >= 0 && q < P) ? hwin[q] : 0.f;
       v[n1] = make_float2(x[n1].x * h, x[n1].y * h);
     }
-    fft_inreg<P1>(v);
+    dft_any<P1>(v);
+    if (n2 < P2) {
 #pragma unroll
-    for (int k1 = 0; k1 < P1; ++k1) {
-      const float2 y = (k1 == 0) ? v[k1] : cmul(v[k1], tw[k1 * n2]);
-      ybuf[(k1 * P2 + n2) * RT + col] = y;
+      for (int k1 = 0; k1 < P1; ++k1) {
+        const float2 y = (k1 == 0) ? v[k1] : cmul(v[k1], tw[k1 * n2]);
+        ybuf[(k1 * P2 + n2) * RT + col] = y;
+      }
     }
     __syncthreads();
     const int dof = t * d.C + c;
@@ -76,8 +101,13 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
       float2 z[P2];
 #pragma unroll
       for (int m2 = 0; m2 < P2; ++m2) z[m2] = ybuf[(k1 * P2 + m2) * RT + c3];
-      fft_inreg<P2>(z);
+      dft_any<P2>(z);
       const int r3 = r0 + c3;
+      if (d.tap_rel && t > 0) {
+        // tap t referenced to its own first pulse: times exp(+2 pi i k t / P)
+#pragma unroll
+        for (int k2 = 0; k2 < P2; ++k2) z[k2] = cmulc(z[k2], tw[((k1 + P1 * k2) * t) % P]);
+      }
       if (r3 < d.R) {
         float2* dst = snap + (long long)dof * d.R + r3;
 #pragma unroll
@@ -113,6 +143,7 @@ int doppler_tiles(const Dims& d) {
   switch (d.P) {
     case 32: rt = FftShape<32>::RT; break;
     case 64: rt = FftShape<64>::RT; break;
+    case 100: rt = FftShape<100>::RT; break;
     case 128: rt = FftShape<128>::RT; break;
     case 256: rt = FftShape<256>::RT; break;
     case 512: rt = FftShape<512>::RT; break;
@@ -126,6 +157,7 @@ hipError_t launch_doppler_batched(int P, const ProbDesc* desc, const BatchIndex&
   switch (P) {
     case 32: hipLaunchKernelGGL(doppler_batched_kernel<32>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
     case 64: hipLaunchKernelGGL(doppler_batched_kernel<64>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 100: hipLaunchKernelGGL(doppler_batched_kernel<100>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
     case 128: hipLaunchKernelGGL(doppler_batched_kernel<128>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
     case 256: hipLaunchKernelGGL(doppler_batched_kernel<256>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
     case 512: hipLaunchKernelGGL(doppler_batched_kernel<512>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
@@ -143,6 +175,7 @@ hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipSt
   switch (d.P) {
     case 32: return go(doppler_kernel<32>, FftShape<32>::RT);
     case 64: return go(doppler_kernel<64>, FftShape<64>::RT);
+    case 100: return go(doppler_kernel<100>, FftShape<100>::RT);
     case 128: return go(doppler_kernel<128>, FftShape<128>::RT);
     case 256: return go(doppler_kernel<256>, FftShape<256>::RT);
     case 512: return go(doppler_kernel<512>, FftShape<512>::RT);

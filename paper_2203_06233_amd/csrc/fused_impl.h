@@ -41,15 +41,16 @@ __device__ __forceinline__ void fused_system(const float2* __restrict__ snap, co
 
   const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
   const int D = d.D;
-  const float2* X = snap + (long long)k * D * d.R + (long long)b * d.N;
+  const float2* X = snap + (long long)k * D * d.R;
   floatx4 accR[C::TPW], accI[C::TPW];
-  cov_accumulate<C>(X, d.R, D, d.N, lds, red, accR, accI);
+  cov_accumulate<C>(X, d.R, D, d.N, train_cells(d, b), lds, red, accR, accI);
   const float dl = cov_delta<C>(accR, D, d.eps, dsum, &s_delta);
   __syncthreads();  // the staging buffer is dead: reuse it for R_L
   float2* Rp = reinterpret_cast<float2*>(lds);
   cov_emit<C>(accR, accI, D, dl, [&](int row, int col, float2 v) { Rp[row * (row + 1) / 2 + col] = v; });
   __syncthreads();
-  solve_system<K, REFINE, true>(PackedR{Rp}, Rp, Rp + K::kPacked, steer, wout + (long long)sys * d.S * D,
+  solve_system<K, REFINE, true>(PackedR{Rp}, Rp, Rp + K::kPacked, steer + steer_offset(d, sys),
+                                wout + (long long)sys * d.S * D,
                                 info_out ? info_out + sys : nullptr, d, sh);
 }
 
@@ -104,9 +105,9 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
 
   const int k = sys / d.B, b = sys - (sys / d.B) * d.B;
   const int D = d.D;
-  const float2* X = snap + (long long)k * D * d.R + (long long)b * d.N;
+  const float2* X = snap + (long long)k * D * d.R;
   floatx4 accR[C::TPW], accI[C::TPW];
-  cov_accumulate<C>(X, d.R, D, d.N, lds, red, accR, accI);
+  cov_accumulate<C>(X, d.R, D, d.N, train_cells(d, b), lds, red, accR, accI);
   const float dl = cov_delta<C>(accR, D, d.eps, dsum, &s_delta);
   __syncthreads();
   float2* Rp = reinterpret_cast<float2*>(lds);
@@ -115,7 +116,8 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
   // the packed R_L is dead after the last residual: u of that step is kept
   // there when it fits
   constexpr bool PARK = REFINE && PACK >= NS * NB * 256 * 8;
-  bsolve_system<B, REFINE>(PackedR{Rp}, steer, wout + (long long)sys * d.S * D, info_out ? info_out + sys : nullptr,
+  bsolve_system<B, REFINE>(PackedR{Rp}, steer + steer_offset(d, sys), wout + (long long)sys * d.S * D,
+                           info_out ? info_out + sys : nullptr,
                            d, lds + (REFINE ? PACK : 0), PARK ? Rp : nullptr);
 }
 

@@ -72,6 +72,10 @@ hipError_t launch_fused16(const Dims& d, const float2* snap, const float2* steer
 hipError_t launch_fused32(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
                           hipStream_t st);
 
+// detect[P][S][R] (1 = detection) from power[P][S][R] by CA-CFAR along range.
+hipError_t launch_cfar(const Dims& d, int n_ref, int n_guard, double alpha, const float* power,
+                       unsigned char* detect, hipStream_t st);
+
 // power[P][S][R] (and y if non-null) from W and X.
 hipError_t launch_inner(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
                         hipStream_t st);

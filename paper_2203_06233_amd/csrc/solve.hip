@@ -38,7 +38,8 @@ __global__ __launch_bounds__(16 * TY) void solve_kernel(const float2* __restrict
     for (int i = threadIdx.x / 16; i < d.D; i += TY)
       for (int k = threadIdx.x % 16; k <= i; k += 16) dyn[i * (i + 1) / 2 + k] = src.lower(i, k);
   }
-  solve_system<K, REFINE, K::kPackedInLds>(src, dyn, dyn + (K::kPackedInLds ? K::kPacked : 0), steer,
+  solve_system<K, REFINE, K::kPackedInLds>(src, dyn, dyn + (K::kPackedInLds ? K::kPacked : 0),
+                                           steer + steer_offset(d, sys),
                                            wout + (long long)sys * d.S * d.D,
                                            info_out ? info_out + sys : nullptr, d, sh);
 }

@@ -13,7 +13,7 @@ __global__ __launch_bounds__(64) void wsolve_kernel(const float2* __restrict__ c
                                                     float2* __restrict__ wout, int* __restrict__ info_out, Dims d) {
   __shared__ __align__(16) float2 lds[WsLds<NB, REFINE>::COMPLEX];
   const int sys = blockIdx.x;
-  wsolve_system<NB, NS, REFINE>(cov + (long long)sys * d.D * d.D, steer, wout + (long long)sys * d.S * d.D,
+  wsolve_system<NB, NS, REFINE>(cov + (long long)sys * d.D * d.D, steer + steer_offset(d, sys), wout + (long long)sys * d.S * d.D,
                                 info_out ? info_out + sys : nullptr, d, lds);
 }
 

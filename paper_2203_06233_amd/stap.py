@@ -36,13 +36,19 @@ class Problem(ctypes.Structure):
         ("n_chan", ctypes.c_int32), ("n_pulse", ctypes.c_int32), ("n_range", ctypes.c_int32),
         ("tdof", ctypes.c_int32), ("n_block", ctypes.c_int32), ("n_steer", ctypes.c_int32),
         ("load_eps", ctypes.c_float), ("precision", ctypes.c_int32),
-        ("refine_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("refine_steps", ctypes.c_int32), ("training", ctypes.c_int32),
         ("cube_stride_chan", ctypes.c_int64), ("cube_stride_pulse", ctypes.c_int64),
+        ("guard_cells", ctypes.c_int32), ("tap_phase", ctypes.c_int32),
+        ("steer_per_bin", ctypes.c_int32), ("subarray", ctypes.c_int32),
     ]
 
     @property
+    def channels(self) -> int:
+        return self.n_chan // max(self.subarray, 1)
+
+    @property
     def dof(self) -> int:
-        return self.tdof * self.n_chan
+        return self.tdof * self.channels
 
     @property
     def n_cell(self) -> int:
@@ -51,7 +57,12 @@ class Problem(ctypes.Structure):
     def __repr__(self):
         return (f"Problem(C={self.n_chan}, P={self.n_pulse}, R={self.n_range}, T={self.tdof}, "
                 f"B={self.n_block}, S={self.n_steer}, eps={self.load_eps}, prec={self.precision}, "
-                f"refine={self.refine_steps})")
+                f"refine={self.refine_steps}, training={self.training}, guard={self.guard_cells}, "
+                f"tap_phase={self.tap_phase}, steer_per_bin={self.steer_per_bin})")
+
+
+class CfarParams(ctypes.Structure):
+    _fields_ = [("n_ref", ctypes.c_int32), ("n_guard", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
@@ -68,6 +79,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "stap_inner_products": [P(Problem), vp, vp, vp, vp, vp],
         "stap_run": [P(Problem), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp), P(vp), vp, ctypes.c_size_t, vp],
         "stap_check_problem": [P(Problem)],
+        "stap_cfar": [P(Problem), P(CfarParams), vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -114,11 +126,21 @@ def tune_get(dof: int, n_steer: int, precision: str, refine: int, kind: int = 0)
     return int(_lib.stap_tune_get(kind, dof, n_steer, PREC[precision], refine))
 
 
+TAP_PHASE = {"absolute": 0, "relative": 1}
+
+
 def problem(n_chan: int, n_pulse: int, n_range: int, tdof: int, n_block: int, n_steer: int,
             load_eps: float = 1e-3, precision: str = "fp32", refine_steps: int = 0,
-            cube_stride_chan: int = 0, cube_stride_pulse: int = 0) -> Problem:
+            cube_stride_chan: int = 0, cube_stride_pulse: int = 0, guard: Optional[int] = None,
+            tap_phase: str = "absolute", steer_per_bin: bool = False, n_sub: int = 1) -> Problem:
+    """``guard`` None: each block trains on its own cells; an integer G >= 0:
+    the block and G guard cells per side are excluded from its training.
+    ``n_sub`` > 1: n_chan counts array elements, summed n_sub at a time into
+    the channels the processing sees."""
+    training, guard_cells = (0, 0) if guard is None else (1, int(guard))
     return Problem(n_chan, n_pulse, n_range, tdof, n_block, n_steer, load_eps, PREC[precision],
-                   refine_steps, 0, cube_stride_chan, cube_stride_pulse)
+                   refine_steps, training, cube_stride_chan, cube_stride_pulse, guard_cells,
+                   TAP_PHASE[tap_phase], 1 if steer_per_bin else 0, n_sub if n_sub > 1 else 0)
 
 
 def check_problem(prob: Problem) -> None:
@@ -165,7 +187,8 @@ def _cube_ptr(prob: Problem, cube: torch.Tensor) -> int:
 
 def _sizes(prob: Problem):
     P, D, R, B, S = prob.n_pulse, prob.dof, prob.n_range, prob.n_block, prob.n_steer
-    return dict(snap=P * D * R, cov=P * B * D * D, delta=P * B, steer=S * D, w=P * B * S * D,
+    return dict(snap=P * D * R, cov=P * B * D * D, delta=P * B,
+                steer=(P if prob.steer_per_bin else 1) * S * D, w=P * B * S * D,
                 info=P * B, power=P * S * R, y=P * S * R)
 
 
@@ -258,6 +281,18 @@ def inner_products(prob: Problem, w: torch.Tensor, snap: torch.Tensor, power: Op
                                     _ptr(y, torch.complex64, "y", n["y"]), _stream(stream)),
            "stap_inner_products")
     return (power, y) if want_y else power
+
+
+def cfar(prob: Problem, power: torch.Tensor, n_ref: int, n_guard: int, alpha: float,
+         detect: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """CA-CFAR detection mask detect[P][S][R] uint8 from power[P][S][R]."""
+    if detect is None:
+        detect = _empty((prob.n_pulse, prob.n_steer, prob.n_range), torch.uint8, power)
+    n = _sizes(prob)
+    par = CfarParams(n_ref, n_guard, alpha)
+    _check(_lib.stap_cfar(ctypes.byref(prob), ctypes.byref(par), _ptr(power, torch.float32, "power", n["power"]),
+                          _ptr(detect, torch.uint8, "detect", n["power"]), _stream(stream)), "stap_cfar")
+    return detect
 
 
 def workspace_size(probs: Sequence[Problem]) -> int:

@@ -25,6 +25,8 @@ def host(t):
 
 def prob_of(wl, precision="fp32", refine=0, **kw):
     stap = binding()
+    if wl.n_sub > 1:
+        kw.setdefault("n_sub", wl.n_sub)
     return stap.problem(wl.n_chan, wl.n_pulse, wl.n_range, wl.tdof, wl.n_block, wl.n_steer,
                         load_eps=wl.load_eps, precision=precision, refine_steps=refine, **kw)
 

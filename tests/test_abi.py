@@ -51,7 +51,7 @@ GOOD = dict(n_chan=4, n_pulse=64, n_range=512, tdof=3, n_block=32, n_steer=8)
 
 @pytest.mark.parametrize("change,code", [
     (dict(n_pulse=48), -2), (dict(n_pulse=1024), -2), (dict(n_pulse=16), -2),
-    (dict(n_range=500), -2), (dict(n_range=0), -2), (dict(n_block=0), -2),
+    (dict(n_range=500), -2), (dict(n_range=0), -2), (dict(n_block=0), -2), (dict(n_pulse=100, tdof=3), 0),
     (dict(tdof=0), -2), (dict(tdof=5), -2), (dict(n_chan=65), -2),
     (dict(n_steer=0), -2), (dict(n_steer=65), -2),
     (dict(load_eps=-1.0), -1), (dict(load_eps=float("nan")), -1),
@@ -77,8 +77,66 @@ def test_bad_precision_code(binding):
     p.precision = 7
     assert binding._lib.stap_check_problem(ctypes.byref(p)) == -1
     p.precision = 0
-    p.reserved = 1
+    p.subarray = -1
     assert binding._lib.stap_check_problem(ctypes.byref(p)) == -1
+
+
+def test_paper_cube_shape_and_subarrays(binding):
+    """The paper's cube (100 pulses, 1000 elements, 30000 samples) is valid
+    with subarrays that keep D within the limit, in either nesting of the
+    cube's channel and pulse axes; full element-space DOF is not."""
+    lib = binding._lib
+
+    def code(**kw):
+        p = binding.problem(**kw)
+        return lib.stap_check_problem(ctypes.byref(p))
+
+    paper = dict(n_chan=1000, n_pulse=100, n_range=30000, tdof=3, n_block=250, n_steer=32)
+    assert code(**paper, n_sub=50) == 0
+    assert code(**paper) == -2                      # D = 3000
+    assert code(**paper, n_sub=3) == -2             # 1000 elements are not a multiple of 3
+    assert code(**paper, n_sub=10) == -2            # D = 300
+    # the paper's pulses x channels x samples order: pulse stride C R, channel stride R
+    assert code(**paper, n_sub=50, cube_stride_chan=30000, cube_stride_pulse=1000 * 30000) == 0
+    assert code(**paper, n_sub=50, cube_stride_chan=30000, cube_stride_pulse=999 * 30000) == -2
+    assert code(**dict(GOOD, n_pulse=100)) == 0
+    for P in (96, 200, 1000):
+        assert code(**dict(GOOD, n_pulse=P)) == -2
+    p = binding.problem(**paper, n_sub=50)
+    assert p.dof == 60 and p.channels == 20
+
+
+def test_training_phase_and_steering_fields(binding):
+    """Cell-under-test exclusion, tap phase and per-bin steering are checked
+    on the host: codes out of range, guard cells without exclusion, and
+    blocks that cannot find N training cells outside themselves and their
+    guard cells."""
+    lib = binding._lib
+
+    def code(**kw):
+        p = binding.problem(**dict(GOOD, **kw))
+        return lib.stap_check_problem(ctypes.byref(p))
+
+    assert code(guard=0) == 0 and code(guard=3) == 0
+    assert code(tap_phase="relative") == 0 and code(steer_per_bin=True) == 0
+    # N = 16, R = 512: interior blocks need R - N - 2G >= N
+    assert code(guard=(512 - 32) // 2) == 0
+    assert code(guard=(512 - 32) // 2 + 1) == -2
+    # a single block has no cells outside itself
+    assert code(n_block=1, n_range=64, guard=0) == -2
+    # two blocks of N: each trains on the other (G = 0 only)
+    assert code(n_block=2, n_range=64, guard=0) == 0
+    assert code(n_block=2, n_range=64, guard=1) == -2
+    for field, value in (("training", 2), ("training", -1), ("tap_phase", 2), ("steer_per_bin", 2),
+                         ("guard_cells", -1)):
+        p = binding.problem(**GOOD)
+        setattr(p, field, value)
+        if field == "guard_cells":
+            p.training = 1
+        assert lib.stap_check_problem(ctypes.byref(p)) == -1, field
+    p = binding.problem(**GOOD)
+    p.guard_cells = 2  # guard cells without exclusion
+    assert lib.stap_check_problem(ctypes.byref(p)) == -1
 
 
 def test_entry_points_reject_before_touching_the_device(binding):
@@ -164,7 +222,7 @@ def test_workspace_size_formula(binding):
 
     def up(x):
         return (x + 255) // 256 * 256
-    table = 128  # one problem descriptor
+    table = 136  # one problem descriptor (the kernels' copy of the shapes and pointers)
     per = up(P * D * R * 8) + up(P * B * S * D * 8) + up(P * B * 4)
     cov = up(P * B * D * D * 8) + up(P * B * 4)
     # D <= 96 and S <= 32: the one-wave stage route may run, covariance and delta included
