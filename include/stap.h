@@ -248,6 +248,30 @@ typedef struct stap_cfar_params {
 stap_status stap_cfar(const stap_problem* prob, const stap_cfar_params* cfar,
                       const float* power, uint8_t* detect, void* stream);
 
+/* Maximum stap_workspace_size() of a stap_run_noalloc call (256 MiB). */
+#define STAP_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+
+/* stap_run for callers that cannot allocate device memory: code under graph
+ * capture, tight serving loops, hosts whose rules forbid hipMalloc.  Same
+ * arguments, layouts, ownership, results and errors as stap_run, without the
+ * workspace: the scratch memory (snapshots, and where stap_run would put
+ * them the covariance, weights and status) is a fixed array of
+ * STAP_NOALLOC_MAX_BYTES in the library's device code, one copy per GPU,
+ * held until the process ends.  The call allocates and frees nothing, does
+ * not create streams or graphs, and launches the kernels directly on
+ * `stream` (several cubes: the batched launch chain, never the cached graph).
+ *   Errors: STAP_ERR_WORKSPACE when stap_workspace_size(probs, n_probs)
+ *   exceeds STAP_NOALLOC_MAX_BYTES; otherwise as stap_run.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind; nothing in it needs to start at zero.  Calls that overlap in time
+ * on the same GPU (several streams or host threads) race on the array and
+ * must be serialised by the caller. */
+stap_status stap_run_noalloc(const stap_problem* probs, int32_t n_probs,
+                             const stap_cf32* const* cubes,
+                             const stap_cf32* const* steers,
+                             float* const* powers, stap_cf32* const* weights,
+                             int32_t* const* info, void* stream);
+
 /* Kernel-variant selection, written by the autotuner (tune.py) and read by
  * stap_run and stap_covariance_solve (kind 0, the fused covariance->solve
  * kernel) and by stap_solve_weights and the stage path of stap_run (kind 1).

@@ -240,9 +240,36 @@ hipError_t upload_table(stap::ProbDesc* table, const std::vector<stap::ProbDesc>
   return hipSuccess;
 }
 
+// Scratch memory of stap_run_noalloc: a fixed-size array in the library's
+// device code object, one copy per GPU, held until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = STAP_NOALLOC_MAX_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];
+
+stap_status scratch_of_current_device(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return STAP_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return STAP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return STAP_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return STAP_OK;
+}
+
 // stap_run after argument checks: ws0 is a workspace of at least
 // stap_workspace_size() bytes.  `graphs_ok` allows the batched chain to be
-// replayed from the graph cache.
+// replayed from the graph cache (instantiating a graph and creating its
+// capture stream allocate, so the no-allocation entry point passes false).
 stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
                      const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
                      int32_t* const* info, char* const ws0, hipStream_t st, bool graphs_ok) {
@@ -480,6 +507,17 @@ stap_status stap_run(const stap_problem* probs, int32_t n_probs, const stap_cf32
   if (!aligned(workspace, kAlign)) return STAP_ERR_ALIGN;
   return run_impl(probs, n_probs, cubes, steers, powers, weights, info, static_cast<char*>(workspace),
                   (hipStream_t)stream, true);
+}
+
+stap_status stap_run_noalloc(const stap_problem* probs, int32_t n_probs, const stap_cf32* const* cubes,
+                             const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
+                             int32_t* const* info, void* stream) {
+  stap_status s = check_run(probs, n_probs, cubes, steers, powers, weights, info);
+  if (s != STAP_OK) return s;
+  if (stap_workspace_size(probs, n_probs) > kScratchBytes) return STAP_ERR_WORKSPACE;
+  char* ws = nullptr;
+  if ((s = scratch_of_current_device(&ws)) != STAP_OK) return s;
+  return run_impl(probs, n_probs, cubes, steers, powers, weights, info, ws, (hipStream_t)stream, false);
 }
 
 void stap_use_graphs(int32_t enable) { g_use_graphs = enable != 0; }

@@ -80,6 +80,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "stap_run": [P(Problem), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp), P(vp), vp, ctypes.c_size_t, vp],
         "stap_check_problem": [P(Problem)],
         "stap_cfar": [P(Problem), P(CfarParams), vp, vp, vp],
+        "stap_run_noalloc": [P(Problem), ctypes.c_int32, P(vp), P(vp), P(vp), P(vp), P(vp), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -335,6 +336,31 @@ class Runner:
         _check(_lib.stap_run(self._arr, n, cp, sp, pp, wp, ip, self.workspace.data_ptr(),
                              self.workspace.numel(), _stream(stream)), "stap_run")
         return powers
+
+
+NOALLOC_MAX_BYTES = 256 << 20
+
+
+def run_noalloc(probs: Sequence[Problem], cubes: Sequence[torch.Tensor], steers: Sequence[torch.Tensor],
+                powers: Sequence[torch.Tensor], weights: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                info: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None) -> None:
+    """stap_run_noalloc: the chain on the library's fixed scratch array, with
+    caller-allocated outputs (``powers`` is required; nothing is allocated)."""
+    n = len(probs)
+    if len(cubes) != n or len(steers) != n or len(powers) != n:
+        raise ValueError("one cube, steering set and power array per problem")
+    for name, lst in (("weights", weights), ("info", info)):
+        if lst is not None and len(lst) != n:
+            raise ValueError(f"{name}: one entry per problem")
+    arr = (Problem * n)(*probs)
+    sz = [_sizes(p) for p in probs]
+    VP = ctypes.c_void_p * n
+    cp = VP(*[_cube_ptr(p, c) for p, c in zip(probs, cubes)])
+    sp = VP(*[_ptr(s, torch.complex64, "steer", z["steer"]) for s, z in zip(steers, sz)])
+    pp = VP(*[_ptr(p, torch.float32, "power", z["power"]) for p, z in zip(powers, sz)])
+    wp = VP(*[_ptr(x, torch.complex64, "weights", z["w"]) for x, z in zip(weights, sz)]) if weights is not None else None
+    ip = VP(*[_ptr(x, torch.int32, "info", z["info"]) for x, z in zip(info, sz)]) if info is not None else None
+    _check(_lib.stap_run_noalloc(arr, n, cp, sp, pp, wp, ip, _stream(stream)), "stap_run_noalloc")
 
 
 def run(probs: Sequence[Problem], cubes, steers, **kw) -> List[torch.Tensor]:

@@ -179,6 +179,23 @@ def test_run_rejects_before_touching_the_device(binding):
     assert lib.stap_run(probs, 0, fake, fake, fake, None, None, ctypes.c_void_p(0x100000), need, None) == -1
 
 
+def test_noalloc_rejects_on_the_host(binding):
+    """stap_run_noalloc checks its arguments and the fixed scratch size before
+    any HIP call: a cube whose workspace exceeds STAP_NOALLOC_MAX_BYTES gets
+    STAP_ERR_WORKSPACE, bad pointers their usual codes."""
+    lib = binding._lib
+    one = ctypes.c_void_p * 1
+    fake = one(0x10000)
+    big = (binding.Problem * 1)(binding.problem(n_chan=32, n_pulse=256, n_range=16384, tdof=3, n_block=128,
+                                                n_steer=32))
+    assert binding.workspace_size(list(big)) > binding.NOALLOC_MAX_BYTES
+    assert lib.stap_run_noalloc(big, 1, fake, fake, fake, None, None, None) == -4
+    small = (binding.Problem * 1)(binding.problem(**GOOD))
+    assert lib.stap_run_noalloc(small, 1, one(0x10004), fake, fake, None, None, None) == -3
+    assert lib.stap_run_noalloc(small, 0, fake, fake, fake, None, None, None) == -1
+    assert lib.stap_run_noalloc(small, 1, None, fake, fake, None, None, None) == -1
+
+
 def test_tuning_table(binding):
     lib = binding._lib
     saved = binding.tune_get(96, 32, "bf16", 1)
