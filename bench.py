@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds-single", type=float, default=8.0,
+                    help="seconds of the single-threaded oracle sample")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the leg on the paper's own cube (100 pulses x 1000 channels x 30000 samples)")
+    ap.add_argument("--no-cfar", action="store_true", help="skip the CA-CFAR leg")
     return ap.parse_args()
 
 
@@ -71,6 +76,8 @@ def kernel_work(wl, precision, refine):
     chol = (4.0 / 3.0) * D ** 3 * sysn
     solves = 8.0 * D * D * S * sysn
     cov_key = {"fp32": "fp32", "bf16": "bf16", "fp8": "fp8"}[precision]
+    # the inner products run on BF16 matrix cores on the mixed paths
+    inner_key = "fp32" if precision == "fp32" else "bf16"
     return {
         "doppler": dict(bytes=cube_b + snap_b, fp32=5.0 * T * C * R * P * np.log2(P)),
         "covariance": {"bytes": snap_b + cov_b, cov_key: herm},
@@ -78,11 +85,20 @@ def kernel_work(wl, precision, refine):
         # fused: snapshots in, weights out; covariance products plus the solve
         "covariance_solve": {"bytes": snap_b + w_b, cov_key: herm,
                              "fp32": chol + solves * (1 + refine), "fp64": solves * refine},
-        "inner": dict(bytes=snap_b + w_b + pw_b, fp32=8.0 * S * D * N * sysn),
+        "inner": {"bytes": snap_b + w_b + pw_b, inner_key: 8.0 * S * D * N * sysn},
     }
 
 
-PEAKS = {"fp32": FP32_PEAK, "bf16": BF16_PEAK, "fp8": 5.0e15, "fp64": FP64_PEAK}
+def cfar_work(wl, n_ref):
+    """CA-CFAR on the power map: power in (4 B) and mask out (1 B) per cell,
+    2 n_ref FP64 additions per cell."""
+    cells = wl.n_pulse * wl.n_steer * wl.n_range
+    return {"bytes": 5 * cells, "fp64_add": 2.0 * n_ref * cells}
+
+
+# fp64_add: plain FP64 additions, one per lane per instruction, so half the
+# FMA-counted FP64 peak
+PEAKS = {"fp32": FP32_PEAK, "bf16": BF16_PEAK, "fp8": 5.0e15, "fp64": FP64_PEAK, "fp64_add": FP64_PEAK / 2}
 
 
 def roofline_of(name, work, sec):
@@ -99,6 +115,8 @@ def roofline_of(name, work, sec):
     ach = flops / sec
     peak = flops / t_cmp
     bound = "mfma" if name in ("covariance", "inner") else "alu"
+    if name == "cfar":
+        bound = "alu"
     return dict(bound=bound, achieved=ach / 1e12, peak=peak / 1e12, unit="TFLOP/s", frac=ach / peak)
 
 
@@ -242,6 +260,14 @@ def main():
         pwr = stap.inner_products(prob, wts, snap)
         calls["inner"] = lambda: stap.inner_products(prob, wts, snap, pwr)
         work = kernel_work(w, args.precision, args.refine)
+        if not args.no_cfar:
+            # CA-CFAR on the power map (16 reference and 2 guard cells per
+            # side, Pfa 1e-4 on exponential noise): the step after the chain
+            from oracle import cfar as ocfar  # the closed-form threshold factor only
+            alpha = ocfar.alpha_for_pfa(32, 1e-4)
+            det = stap.cfar(prob, pwr, 16, 2, alpha)
+            calls["cfar"] = lambda: stap.cfar(prob, pwr, 16, 2, alpha, det)
+            work["cfar"] = cfar_work(w, 16)
         ksteps = max(1, min(args.steps, 20))
         for name, fn in calls.items():
             for _ in range(2):
@@ -254,11 +280,12 @@ def main():
             torch.cuda.synchronize()
             sec = e0.elapsed_time(e1) / ksteps / 1e3
             kern[name] = dict(ms=sec * 1e3, **roofline_of(name, work[name], sec))
-        dom = max(kern, key=lambda k: kern[k]["ms"])
+        dom = max((k for k in kern if k != "cfar"), key=lambda k: kern[k]["ms"])
         r = kern[dom]
         roof = dict(kernel=dom, bound=r["bound"], achieved=r["achieved"], peak=r["peak"], unit=r["unit"],
                     frac=r["frac"], traffic=measured_traffic(dom, w.name, args.precision, args.refine))
         del snap, wts, inf, pwr, cov
+        calls.clear()
         torch.cuda.empty_cache()
 
     # accuracy against the FP64 oracle on sampled training blocks
@@ -298,6 +325,58 @@ def main():
         cpu = dict(value=nb * N * w.dof / el, unit="range-cell*DOF/s", cores=threads, kind="oracle",
                    sample=f"{nb} training blocks of {N} cells x all {w.n_pulse} bins (oracle.run_block), "
                           f"{el:.1f} s; host os.cpu_count()={os.cpu_count()}")
+        # the same oracle on one thread (the analogue of sequential NumPy)
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                nb1, t1 = 0, time.perf_counter()
+                while True:
+                    b = (nb1 * 53 + 11) % w.n_block
+                    orc.run_block(cubes_np[0][:, :, b * N:(b + 1) * N], steers_np[0], w.tdof, w.load_eps)
+                    nb1 += 1
+                    el1 = time.perf_counter() - t1
+                    if (el1 > args.cpu_seconds_single and nb1 >= 1) or nb1 >= w.n_block:
+                        break
+            cpu["single_thread"] = dict(value=nb1 * N * w.dof / el1, cores=1,
+                                        sample=f"{nb1} training blocks, {el1:.1f} s, BLAS limited to one thread")
+        except ImportError:
+            pass
+
+    # the paper's own cube (100 pulses x 1000 channels x 30000 samples, stored
+    # pulses x channels x samples), 1000 elements in 20 subarrays (D = 60):
+    # one stap_run per cube, resident in HBM; values are device-generated
+    # complex Gaussian noise (the kernels' time does not depend on them)
+    paper = None
+    if not args.no_paper and len(wls) == 1:
+        del cubes
+        torch.cuda.empty_cache()
+        wp = synth.PAPER
+        g = torch.Generator(device=dev)
+        g.manual_seed(wp.seed)
+        pcube = torch.randn((wp.n_pulse, wp.n_chan, wp.n_range), dtype=torch.complex64, device=dev, generator=g)
+        pv = torch.from_numpy(synth.steering(wp)).to(dev)
+        pprob = stap.problem(wp.n_chan, wp.n_pulse, wp.n_range, wp.tdof, wp.n_block, wp.n_steer,
+                             load_eps=wp.load_eps, precision=args.precision, refine_steps=args.refine,
+                             cube_stride_chan=wp.n_range, cube_stride_pulse=wp.n_chan * wp.n_range, n_sub=wp.n_sub)
+        prun = stap.Runner([pprob], device=dev)
+        ppow = [torch.empty((wp.n_pulse, wp.n_steer, wp.n_range), dtype=torch.float32, device=dev)]
+        for _ in range(2):
+            prun.run([pcube], [pv], powers=ppow)
+        torch.cuda.synchronize()
+        psteps = 5
+        t = time.perf_counter()
+        for _ in range(psteps):
+            prun.run([pcube], [pv], powers=ppow)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t) / psteps * 1e3
+        paper = dict(workload=wp.name, layout="pulses x channels x samples (strides)", subarray=wp.n_sub,
+                     D=wp.dof, B=wp.n_block, N=wp.n_cell, S=wp.n_steer, precision=args.precision,
+                     refine_steps=args.refine, ms_per_cube=pms, cubes_per_s=1e3 / pms,
+                     real_time_cubes_per_s=33.3, value=wp.cells_dof / (pms * 1e-3), steps=psteps,
+                     cube_gb=wp.n_pulse * wp.n_chan * wp.n_range * 8 / 1e9,
+                     data="device-generated CN(0,1) noise of the cube's shape")
+        del pcube, ppow, prun
+        torch.cuda.empty_cache()
 
     name = args.workload if len(wls) > 1 else wls[0].name
     value = cells_dof / wall_m
@@ -327,6 +406,7 @@ def main():
         "kernels": kern,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "paper_cube": paper,
         "gen_seconds": gen_s,
     }
     print(json.dumps(line), flush=True)

@@ -274,7 +274,12 @@ stap_status stap_run_noalloc(const stap_problem* probs, int32_t n_probs,
 
 /* Kernel-variant selection, written by the autotuner (tune.py) and read by
  * stap_run and stap_covariance_solve (kind 0, the fused covariance->solve
- * kernel) and by stap_solve_weights and the stage path of stap_run (kind 1).
+ * kernel), by stap_solve_weights and the stage path of stap_run (kind 1),
+ * by stap_covariance and the stage path of stap_run (kind 2: waves per
+ * system, 4, 8 or 16 where the DOF class offers them, every choice giving
+ * the same covariance bit for bit) and by stap_inner_products and the
+ * single-cube stap_run (kind 3: 1, 2 or 4 range tiles of 16 cells per wave
+ * step, at most 2 on the split-BF16 form; the same output bit for bit).
  * An entry applies to the shape class containing (dof, n_steer): dof classes
  * end at 16, 32, 48, 64, 96, 128, 160, 192 and steering classes at 16, 32, 64.
  * variant: 0 = built-in default;

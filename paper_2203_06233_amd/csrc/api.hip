@@ -101,12 +101,18 @@ stap_status hip_status(hipError_t e) { return e == hipSuccess ? STAP_OK : STAP_E
 
 // Kernel-variant table written by the autotuner: [kind][dof class][steer
 // class][precision][refine] -> variant (0 = built-in default).  Kind 0 is
-// the fused covariance -> solve of stap_run, kind 1 the stage weight solve.
+// the fused covariance -> solve of stap_run, kind 1 the stage weight solve,
+// kind 2 the stage covariance (waves per system), kind 3 the inner products
+// (range tiles per wave step).
 constexpr int kDofClass[] = {16, 32, 48, 64, 96, 128, 160, 192};
 constexpr int kSteerClass[] = {16, 32, 64};
-constexpr int kKinds = 2;
+constexpr int kKinds = 4;
 int8_t g_tune[kKinds][8][3][3][2];
-bool valid_variant(int v) { return v == 0 || v == 1 || v == 4 || v == 8 || v == 16 || v == 32; }
+bool valid_variant(int kind, int v) {
+  if (kind == 2) return v == 0 || v == 4 || v == 8 || v == 16;
+  if (kind == 3) return v == 0 || v == 1 || v == 2 || v == 4;
+  return v == 0 || v == 1 || v == 4 || v == 8 || v == 16 || v == 32;
+}
 
 int dof_class(int d) {
   for (int i = 0; i < 8; ++i)
@@ -306,15 +312,15 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
       wsp += p.total();
       hipError_t e = stap::launch_doppler(d, pd.cube, pd.snap, st);
       if (one_wave_route(d)) {
-        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);
+        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st, tuned(2, d));
         if (e == hipSuccess) e = stap::launch_wsolve(d, cov, pd.steer, pd.w, pd.info, st);
       } else if (stap::fused_supported(d)) {
         if (e == hipSuccess) e = stap::launch_fused(d, pd.snap, pd.steer, pd.w, pd.info, st, fused_variant(d));
       } else {
-        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st);
+        if (e == hipSuccess) e = stap::launch_covariance(d, pd.snap, cov, delta, st, tuned(2, d));
         if (e == hipSuccess) e = stage_solve(d, cov, pd.steer, pd.w, pd.info, st);
       }
-      if (e == hipSuccess) e = stap::launch_inner(d, pd.w, pd.snap, pd.power, nullptr, st);
+      if (e == hipSuccess) e = stap::launch_inner(d, pd.w, pd.snap, pd.power, nullptr, st, tuned(3, d));
       if (e != hipSuccess) return STAP_ERR_HIP;
     }
     return STAP_OK;
@@ -435,7 +441,8 @@ stap_status stap_covariance(const stap_problem* prob, const stap_cf32* snap, sta
   if (!aligned(snap, 8) || !aligned(cov, 8) || !aligned(delta, 4)) return STAP_ERR_ALIGN;
   const Dims d = dims_of(prob);
   return hip_status(stap::launch_covariance(d, reinterpret_cast<const float2*>(snap),
-                                            reinterpret_cast<float2*>(cov), delta, (hipStream_t)stream));
+                                            reinterpret_cast<float2*>(cov), delta, (hipStream_t)stream,
+                                            tuned(2, d)));
 }
 
 stap_status stap_solve_weights(const stap_problem* prob, const stap_cf32* cov, const stap_cf32* steer,
@@ -471,7 +478,7 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w, co
   const Dims d = dims_of(prob);
   return hip_status(stap::launch_inner(d, reinterpret_cast<const float2*>(w),
                                        reinterpret_cast<const float2*>(snap), power,
-                                       reinterpret_cast<float2*>(y), (hipStream_t)stream));
+                                       reinterpret_cast<float2*>(y), (hipStream_t)stream, tuned(3, d)));
 }
 
 stap_status stap_cfar(const stap_problem* prob, const stap_cfar_params* cfar, const float* power, uint8_t* detect,
@@ -540,7 +547,7 @@ stap_status stap_tune_set(int32_t kind, int32_t dof, int32_t n_steer, int32_t pr
   const int dc = dof_class(dof), sc = steer_class(n_steer);
   if (kind < 0 || kind >= kKinds || dc < 0 || sc < 0 || precision < 0 || precision > 2 || refine < 0)
     return STAP_ERR_ARG;
-  if (!valid_variant(variant)) return STAP_ERR_ARG;
+  if (!valid_variant(kind, variant)) return STAP_ERR_ARG;
   g_tune[kind][dc][sc][precision][refine > 0 ? 1 : 0] = (int8_t)variant;
   return STAP_OK;
 }

@@ -144,26 +144,44 @@ __device__ __forceinline__ float2 rowb2(float2 v) {
   return make_float2(rowb<J>(v.x), rowb<J>(v.y));
 }
 
+__device__ __forceinline__ double bcast64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Column j of the in-wave factorisation of diag_factor_inv().  Rows and
 // columns at or before j are never read again once column j is done, so the
 // update of A needs no mask: with l = A[m][j] / d_j^2 (unmasked) the lanes
 // take A[m][c] -= l A[j][c], which is right wherever m, c > j and harmless
 // elsewhere.  The inverse is kept with unscaled rows Y (X[m] = Y[m] / d_m):
 // rows below j take Y[m] -= (l_mj / d_j) Y[j]; the lane of row j records
-// 1 / d_j for the final scaling.  There is no branch: after a non-positive
-// pivot the remaining columns run on meaningless values and only the first
-// failing index is kept, so the 16 columns form one straight-line block the
-// compiler can overlap.
+// 1 / d_j for the final scaling.
+//
+// The pivot is taken in FP64: every lane keeps, for its row m, p64 =
+// (loaded diagonal R_mm) - (sum over earlier block columns of |L_mk|^2, FP64
+// sums of the FP32 factor) - (sum over earlier columns of this block of
+// |l_mk|^2, accumulated here in FP64), so d_j^2 = p64 of row j (read from the
+// lane holding the block's diagonal element j) and the status test is
+// p64 > 0 in FP64; the factorisation continues with d_j^2 rounded to FP32.
+// There is no branch: after a non-positive pivot the remaining columns run
+// on meaningless values and only the first failing index is kept, so the 16
+// columns form one straight-line block the compiler can overlap.
 template <int j>
-__device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, float& rsm, int& fail) {
+__device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, float& rsm, int& fail, double& p64) {
   constexpr int jq = j >> 2, ji = j & 3;
-  const float piv = bcast(A.v[ji].x, j + 16 * jq);  // A[j][j], wave-uniform
-  fail = (fail == 0 && !(piv > 0.f)) ? j + 1 : fail;
+  const double piv64 = bcast64(p64, j + 16 * jq);  // row j's FP64 Schur diagonal, wave-uniform
+  fail = (fail == 0 && !(piv64 > 0.0)) ? j + 1 : fail;
+  const float piv = (float)piv64;
   const float rs = __builtin_amdgcn_rsqf(piv), r2 = rs * rs;
   const float2 amj = shfl2(A.v[ji], m + 16 * jq);  // A[m][j]
   const float2 la = make_float2(amj.x * r2, amj.y * r2);  // l_mj / d_j
   const float2 lx = (m > j) ? la : make_float2(0.f, 0.f);
   rsm = (m == j) ? rs : rsm;
+  // l_mj = A[m][j] / d_j in FP32, squared and summed in FP64 for row m
+  const float lr = amj.x * rs, li = amj.y * rs;
+  p64 -= (m > j) ? (double)lr * (double)lr + (double)li * (double)li : 0.0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const float2 rj = rowb2<j>(A.v[t]);  // A[j][c] = conj(A[c][j])
@@ -176,30 +194,55 @@ __device__ __forceinline__ void diag_col(Frag& A, Frag& X, int m, float& rsm, in
   }
 }
 template <int j>
-__device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, float& rsm, int& fail) {
-  diag_col<j>(A, X, m, rsm, fail);
-  if constexpr (j < 15) diag_cols<j + 1>(A, X, m, rsm, fail);
+__device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, float& rsm, int& fail, double& p64) {
+  diag_col<j>(A, X, m, rsm, fail, p64);
+  if constexpr (j < 15) diag_cols<j + 1>(A, X, m, rsm, fail, p64);
 }
 
 // Factor the Hermitian 16 x 16 block A (full, both triangles) as L L^H inside
 // one wave and return X = L^-1 (lower triangular).  Column j: pivot
-// d_j = sqrt(A[j][j]), l_mj = A[m][j] / d_j for m > j, then
-// A[m][c] -= l_mj conj(l_cj) for m, c > j; the inverse is accumulated as
-// X <- L_j^-1 X with L_j the identity carrying column j of L (row j of X
-// divided by d_j, then row m -= l_mj row j), the row divisions deferred.  A[c][j] is read as conj(A[j][c])
+// d_j = sqrt(A[j][j]) (taken in FP64 as above, p64 the lane's starting
+// value for its row: loaded diagonal minus the earlier block columns),
+// l_mj = A[m][j] / d_j for m > j, then A[m][c] -= l_mj conj(l_cj) for
+// m, c > j; the inverse is accumulated as X <- L_j^-1 X with L_j the
+// identity carrying column j of L (row j of X divided by d_j, then row m -=
+// l_mj row j), the row divisions deferred.  A[c][j] is read as conj(A[j][c])
 // from row j, which lives in the same 16-lane row of the wave (a DPP
 // broadcast); only l_mj crosses rows.  Returns 0 or the 1-based index of the
 // first non-positive pivot.
-__device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X) {
+__device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X, double p64) {
   const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
   int fail = 0;
   float rsm = 1.f;
-  diag_cols<0>(A, X, m, rsm, fail);
+  diag_cols<0>(A, X, m, rsm, fail, p64);
 #pragma unroll
   for (int i = 0; i < 4; ++i) X.v[i] = make_float2(X.v[i].x * rsm, X.v[i].y * rsm);
   return fail;
+}
+
+// The lane's own diagonal element of a block in fragment order (lane (m, q)
+// holds X[m][4q + i]; the element (m, m) sits in lane q = m / 4, register
+// m % 4), or 0 on the other lanes.
+__device__ __forceinline__ float frag_diag(const Frag& A) {
+  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+  float v = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v = (m == 4 * q + i) ? A.v[i].x : v;
+  return v;
+}
+
+// Row sums of |X|^2 of a block in fragment order, in FP64, on every lane of
+// the row (lane (m, q) holds row m, columns 4q .. 4q + 3).
+__device__ __forceinline__ double frag_row_norm2(const Acc& x) {
+  double p = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    p += (double)x.re[i] * (double)x.re[i] + (double)x.im[i] * (double)x.im[i];
+  p += __shfl_xor(p, 16);
+  p += __shfl_xor(p, 32);
+  return p;
 }
 
 // Static layout of one system with NB block columns of R_L and NS block rows
@@ -221,12 +264,13 @@ struct BCfg {
   __host__ __device__ static constexpr int mslots(int NB, int NS) { return (NS * NB + NW - 1) / NW; }
   // LDS: exchange blocks (NB + NS + 1 for the factorisation and solves, all
   // NS NB blocks of Z for the refinement residual), the gamma partials
-  // [NB][16 NS] (FP64), a flag
+  // [NB][16 NS] (FP64), a flag, and the FP64 row sums of |L|^2 over the
+  // finished block columns [16 NB] (for the FP64 pivots)
   __host__ __device__ static constexpr size_t xblocks(int NB, int NS) {
     return (size_t)(NB + NS + 1 > NS * NB ? NB + NS + 1 : NS * NB);
   }
   __host__ __device__ static constexpr size_t lds_bytes(int NB, int NS) {
-    return xblocks(NB, NS) * 256 * 8 + (size_t)NB * 16 * NS * 8 + 16;
+    return xblocks(NB, NS) * 256 * 8 + (size_t)NB * 16 * NS * 8 + 16 + (size_t)NB * 16 * 8;
   }
 };
 
@@ -235,12 +279,19 @@ struct BCfg {
 // at dinv and the pivot status at sflag.  The block passes through dinv on
 // its way in and out of the register slot, so the diagonal code exists once
 // and every register slot is addressed by a constant index.
+// The FP64 pivots start from the loaded diagonal of the block (rdg, kept
+// per slot since the load) minus the FP64 row sums of |L|^2 over the earlier
+// block columns (d64, LDS).
 template <int NSL>
-__device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSL], int td, int Jd, bool update, const float2* xb,
-                                               float2* dinv, int* sflag) {
+__device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSL], const float (&rdg)[NSL], int td, int Jd, bool update,
+                                               const float2* xb, const double* d64, float2* dinv, int* sflag) {
+  float rd = 0.f;
 #pragma unroll
   for (int t = 0; t < NSL; ++t)
-    if (td == t) frag_store(dinv, to_frag(acc[t]));
+    if (td == t) {
+      frag_store(dinv, to_frag(acc[t]));
+      rd = rdg[t];
+    }
   Frag A = frag_load(dinv), X;
   if (update) {
     Acc a = to_acc(A);
@@ -248,7 +299,9 @@ __device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSL], int td, int Jd, 
     mma_pqh<true>(a, P, P);
     A = to_frag(a);
   }
-  const int f = diag_factor_inv(A, X);
+  const int m = threadIdx.x & 15;
+  const double p64 = (double)rd - (Jd > 0 ? d64[16 * Jd + m] : 0.0);
+  const int f = diag_factor_inv(A, X, p64);
   frag_store(dinv, X);
 #pragma unroll
   for (int t = 0; t < NSL; ++t)
@@ -288,6 +341,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
   float2* xb = reinterpret_cast<float2*>(xlds);  // exchange blocks, 256 complex each
   double* gpart = reinterpret_cast<double*>(xlds + C::xblocks(NB, NS) * 256 * 8);
   int* sflag = reinterpret_cast<int*>(gpart + NB * 16 * NS);
+  double* d64 = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(sflag) + 16);
   const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   float2* dinv = xb + (size_t)(NB + NS) * 256;
@@ -321,6 +375,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
   }
 
   Acc al[NSL], am[NSM];
+  float rdg[NSL];  // loaded diagonal of the slot's block (diagonal blocks), for the FP64 pivots
   // ---- load R_L blocks (identity beyond D) and M = V^H blocks
 #pragma unroll
   for (int t = 0; t < NSL; ++t) {
@@ -346,6 +401,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
       }
     }
     al[t] = a;
+    rdg[t] = frag_diag(to_frag(a));
   }
 #pragma unroll
   for (int t = 0; t < NSM; ++t) {
@@ -363,6 +419,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
     am[t] = a;
   }
   __syncthreads();  // without REFINE the source may be LDS that the exchange blocks reuse
+  for (int r = tid; r < 16 * NB; r += C::NT) d64[r] = 0.0;  // read from step J = 0 on, after a barrier
 
   // ---- factorisation with the forward solve of the steering rows.  The
   // wave owning diagonal block J+1 applies its last update (from column J)
@@ -383,6 +440,10 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
           mma_pqh<false>(x, P, Q);
           al[t] = x;
           frag_store(xb + lr[t] * 256, to_frag(x));
+          // FP64 row sums of |L|^2 for the pivots of block row lr (one
+          // panel block per block row and step: no other writer)
+          const double pn = frag_row_norm2(x);
+          if (q == 0) d64[16 * lr[t] + m] += pn;
         }
       }
 #pragma unroll
@@ -401,7 +462,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
 #pragma unroll
     for (int t = 0; t < NSL; ++t)
       if (J + 1 < NB && lv[t] && lr[t] == J + 1 && lc[t] == J + 1) tn = t;
-    if (tn >= 0) bs_factor_diag<NSL>(al, tn, J + 1, J >= 0, xb, dinv, sflag);
+    if (tn >= 0) bs_factor_diag<NSL>(al, rdg, tn, J + 1, J >= 0, xb, d64, dinv, sflag);
     if (J >= 0) {
 #pragma unroll
       for (int t = 0; t < NSL; ++t)
@@ -482,8 +543,11 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
       }
       // residual in row form: conj(r) = conj(v) - Z R_L, FP64 MFMA (FP32
       // operands converted exactly).  Every Z block is published; each M
-      // block's owner sums over J with one FP64 accumulator pair, whose lane
-      // (m, q) register i holds column q + 4i of the block.
+      // block's owner sums over J.  Each complex product q p takes three real
+      // products (Gauss): a1 += qr pr, a2 += qi pi, a3 += (qr + qi)(pr + pi),
+      // then Re = a1 - a2 and Im = a3 - a1 - a2 (the FP64 sums qr + qi and
+      // pr + pi of FP32 values are exact).  Lane (m, q) register i of an
+      // accumulator holds column q + 4i of the block.
       __syncthreads();
 #pragma unroll
       for (int t = 0; t < NSM; ++t)
@@ -492,14 +556,14 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
 #pragma unroll
       for (int t = 0; t < NSM; ++t) {
         if (mv[t]) {
-          doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+          doublex4 a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
           const float2* zrow = xb + (size_t)mr[t] * NB * 256 + 2 * lane;
           const int c = 16 * mc[t] + m;
           for (int J = 0; J < NB; ++J) {
 #pragma unroll 1
             for (int s4 = 0; s4 < 4; ++s4) {
               const float2 z = zrow[J * 256 + (s4 & 2) * 64 + (s4 & 1)];  // Z_{N,J}[m][4q + s4]
-              const int r = 16 * J + 4 * q + s4;    // R[r][c], c = 16 I + m
+              const int r = 16 * J + 4 * q + s4;                         // R[r][c], c = 16 I + m
               float2 rv;
               if (r < D && c < D) {
                 rv = c <= r ? src.lower(r, c) : src.lower(c, r);
@@ -508,12 +572,12 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
                 rv = make_float2(r == c ? 1.f : 0.f, 0.f);
               }
               const double qr = rv.x, qi = rv.y, pr = z.x, pi = z.y;
-              cr = mfma64(qr, pr, cr);
-              cr = mfma64(-qi, pi, cr);
-              ci = mfma64(qr, pi, ci);
-              ci = mfma64(qi, pr, ci);
+              a1 = mfma64(qr, pr, a1);
+              a2 = mfma64(qi, pi, a2);
+              a3 = mfma64(qr + qi, pr + pi, a3);
             }
           }
+          const doublex4 cr = a1 - a2, ci = a3 - a1 - a2;
           const int s = 16 * mr[t] + m;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {

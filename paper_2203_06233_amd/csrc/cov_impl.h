@@ -118,10 +118,12 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
   constexpr int PF = (NE + NT - 1) / NT;
   constexpr int PV = MODE == 1 ? 2 : 1;
   float2 pf[PF][PV];
-  // One run of training cells (the block itself): contiguous loads.  Two
-  // runs (cells under test excluded): each cell through the map.  The test is
-  // uniform over the workgroup.
-  const bool one_run = cm.nl >= N;
+  // Training cell c lives at lo[c] for c < nl and at hi[c] beyond (both
+  // bases workgroup-uniform; in block mode nl = N and only lo is used).  A
+  // pair of cells straddles the two runs only at c = nl - 1.
+  const float2* const lo = X + cm.a0;
+  const float2* const hi = X + (cm.a1 - cm.nl);
+  const int nl = cm.nl;
   auto load_chunk = [&](int c0) {
     const int nc = min(kCovChunk, N - c0);
 #pragma unroll
@@ -131,14 +133,15 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
         const int row = e / (kCovChunk / 2), cp = e % (kCovChunk / 2);
         float2 v0 = make_float2(0.f, 0.f), v1 = v0;
         if (e < NE && row < D) {
-          const float2* xr = X + (long long)row * rstride;
-          if (one_run) {
-            const float2* src = xr + cm.a0 + c0 + 2 * cp;
+          const int c = c0 + 2 * cp;
+          const long long ro = (long long)row * rstride + c;
+          if (c + 1 != nl) {
+            const float2* src = (c < nl ? lo : hi) + ro;
             if (2 * cp < nc) v0 = src[0];
             if (2 * cp + 1 < nc) v1 = src[1];
           } else {
-            if (2 * cp < nc) v0 = xr[cm.cell(c0 + 2 * cp)];
-            if (2 * cp + 1 < nc) v1 = xr[cm.cell(c0 + 2 * cp + 1)];
+            if (2 * cp < nc) v0 = lo[ro];
+            if (2 * cp + 1 < nc) v1 = hi[ro + 1];
           }
         }
         pf[i][0] = v0;
@@ -146,7 +149,8 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
       } else {
         const int row = e / kCovChunk, cc = e % kCovChunk;
         float2 v = make_float2(0.f, 0.f);
-        if (e < NE && row < D && cc < nc) v = X[(long long)row * rstride + cm.cell(c0 + cc)];
+        const int c = c0 + cc;
+        if (e < NE && row < D && cc < nc) v = (c < nl ? lo : hi)[(long long)row * rstride + c];
         pf[i][0] = v;
       }
     }

@@ -91,14 +91,22 @@ hipError_t go_cov(const Dims& d, const float2* snap, float2* cov, float* delta, 
 
 }  // namespace
 
+// Waves per system: the tuned choice where the DOF class offers one (48 and
+// 64: 4 or 8; 96: 4, 8 or 16; 128: 8 or 16), else the default of the class.
+// Every choice computes each output tile the same way, only the assignment
+// of tiles to waves differs, so the covariance is the same bit for bit.
 hipError_t launch_covariance(const Dims& d, const float2* snap, float2* cov, float* delta,
-                             hipStream_t st) {
+                             hipStream_t st, int nw) {
   if (d.D <= 16) return go_cov<16, 1>(d, snap, cov, delta, st);
   if (d.D <= 32) return go_cov<32, 2>(d, snap, cov, delta, st);
-  if (d.D <= 48) return go_cov<48, 4>(d, snap, cov, delta, st);
-  if (d.D <= 64) return go_cov<64, 4>(d, snap, cov, delta, st);
-  if (d.D <= 96) return go_cov<96, 8>(d, snap, cov, delta, st);
-  if (d.D <= 128) return go_cov<128, 8>(d, snap, cov, delta, st);
+  if (d.D <= 48) return nw == 8 ? go_cov<48, 8>(d, snap, cov, delta, st) : go_cov<48, 4>(d, snap, cov, delta, st);
+  if (d.D <= 64) return nw == 8 ? go_cov<64, 8>(d, snap, cov, delta, st) : go_cov<64, 4>(d, snap, cov, delta, st);
+  if (d.D <= 96) {
+    if (nw == 4) return go_cov<96, 4>(d, snap, cov, delta, st);
+    if (nw == 16) return go_cov<96, 16>(d, snap, cov, delta, st);
+    return go_cov<96, 8>(d, snap, cov, delta, st);
+  }
+  if (d.D <= 128) return nw == 16 ? go_cov<128, 16>(d, snap, cov, delta, st) : go_cov<128, 8>(d, snap, cov, delta, st);
   return go_cov<192, 16>(d, snap, cov, delta, st);
 }
 

@@ -63,9 +63,13 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
   float2 x[P1];
 #pragma unroll
   for (int n1 = 0; n1 < P1; ++n1) x[n1] = make_float2(0.f, 0.f);
-  if (live) {
-    // channel c is the sum of array elements c*sub .. c*sub + sub - 1 (one
-    // element without subarrays), added in element order
+  if (live && d.sub == 1) {
+    const float2* src = cube + (long long)c * d.sc + r;
+#pragma unroll
+    for (int n1 = 0; n1 < P1; ++n1) x[n1] = src[(long long)(P2 * n1 + n2) * d.sp];
+  } else if (live) {
+    // channel c is the sum of array elements c*sub .. c*sub + sub - 1,
+    // added in element order
     for (int e = 0; e < d.sub; ++e) {
       const float2* src = cube + (long long)(c * d.sub + e) * d.sc + r;
 #pragma unroll

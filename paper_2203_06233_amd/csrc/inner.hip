@@ -21,7 +21,7 @@ namespace stap {
 
 namespace {
 
-template <int ST, int DP>
+template <int ST, int DP, int RTW = 2>
 __device__ __forceinline__ void inner_system(const float2* __restrict__ wts, const float2* __restrict__ snap,
                                              float* __restrict__ power, float2* __restrict__ yout,
                                              const Dims& d, int sys) {
@@ -39,9 +39,10 @@ __device__ __forceinline__ void inner_system(const float2* __restrict__ wts, con
   __syncthreads();
   const float2* X = snap + (long long)k * D * d.R + (long long)b * N;
   const int ntile = (N + 15) / 16;
-  // each wave takes RTW range tiles at a time; the snapshot loads of the
-  // next 16-row chunk are issued before the MFMAs of the current one
-  constexpr int RTW = 2;
+  // each wave takes RTW range tiles at a time (a tuning choice: more tiles
+  // give more independent MFMA chains and loads in flight, fewer give more
+  // waves work); the snapshot loads of the next 16-row chunk are issued
+  // before the MFMAs of the current one
   for (int rt0 = wave * RTW; rt0 < ntile; rt0 += 4 * RTW) {
     int r[RTW];
     bool live[RTW];
@@ -121,7 +122,7 @@ __device__ __forceinline__ floatx4 mfma_bf16x(uint4 a, uint4 b, floatx4 c) {
 
 // Split-BF16 variant.  LDS holds the weights as six planes
 // [re h, re m, re l, im h, im m, im l][s][d] (d padded to DP, pitch DP + 8).
-template <int ST, int DP>
+template <int ST, int DP, int RTW = 1>
 __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts, const float2* __restrict__ snap,
                                                   float* __restrict__ power, float2* __restrict__ yout,
                                                   const Dims& d, int sys) {
@@ -157,61 +158,78 @@ __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts
   const int ntile = (N + 15) / 16;
   constexpr int PA[5] = {0, 1, 0, 2, 1};
   constexpr int PB[5] = {1, 0, 2, 0, 1};
-  for (int rt = wave; rt < ntile; rt += 4) {
-    const int r = rt * 16 + (lane & 15);
-    const bool live = r < N;
-    floatx4 accR[ST], accI[ST], corR[ST], corI[ST];
+  // each wave takes RTW range tiles at a time (a tuning choice, as in the
+  // FP32 form)
+  for (int rt0 = wave * RTW; rt0 < ntile; rt0 += 4 * RTW) {
+    int r[RTW];
+    bool live[RTW];
 #pragma unroll
-    for (int t = 0; t < ST; ++t) {
-      accR[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-      accI[t] = accR[t];
-      corR[t] = accR[t];
-      corI[t] = accR[t];
+    for (int w = 0; w < RTW; ++w) {
+      r[w] = (rt0 + w) * 16 + (lane & 15);
+      live[w] = (rt0 + w < ntile) && r[w] < N;
     }
+    floatx4 accR[RTW][ST], accI[RTW][ST], corR[RTW][ST], corI[RTW][ST];
+#pragma unroll
+    for (int w = 0; w < RTW; ++w)
+#pragma unroll
+      for (int t = 0; t < ST; ++t) {
+        accR[w][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        accI[w][t] = accR[w][t];
+        corR[w][t] = accR[w][t];
+        corI[w][t] = accR[w][t];
+      }
 #pragma unroll 1
     for (int q0 = 0; q0 < DP; q0 += 32) {
       // B operand: X[q0 + 8*(lane/16) + j][r], j = 0..7, split into 3 terms
-      unsigned int xb[6][4];
+      uint4 Bv[RTW][6];
 #pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        const int q = q0 + 8 * (lane >> 4) + j;
-        const float2 x0 = (live && q < D) ? X[(long long)q * d.R + r] : make_float2(0.f, 0.f);
-        const float2 x1 = (live && q + 1 < D) ? X[(long long)(q + 1) * d.R + r] : make_float2(0.f, 0.f);
-        split3x2(x0.x, x1.x, xb[0][j / 2], xb[1][j / 2], xb[2][j / 2]);
-        split3x2(x0.y, x1.y, xb[3][j / 2], xb[4][j / 2], xb[5][j / 2]);
+      for (int w = 0; w < RTW; ++w) {
+        unsigned int xb[6][4];
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          const int q = q0 + 8 * (lane >> 4) + j;
+          const float2 x0 = (live[w] && q < D) ? X[(long long)q * d.R + r[w]] : make_float2(0.f, 0.f);
+          const float2 x1 = (live[w] && q + 1 < D) ? X[(long long)(q + 1) * d.R + r[w]] : make_float2(0.f, 0.f);
+          split3x2(x0.x, x1.x, xb[0][j / 2], xb[1][j / 2], xb[2][j / 2]);
+          split3x2(x0.y, x1.y, xb[3][j / 2], xb[4][j / 2], xb[5][j / 2]);
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) Bv[w][p] = make_uint4(xb[p][0], xb[p][1], xb[p][2], xb[p][3]);
       }
-      uint4 Bv[6];
-#pragma unroll
-      for (int p = 0; p < 6; ++p) Bv[p] = make_uint4(xb[p][0], xb[p][1], xb[p][2], xb[p][3]);
 #pragma unroll
       for (int t = 0; t < ST; ++t) {
         const int o = (t * 16 + (lane & 15)) * (PITCH / 8) + q0 / 8 + (lane >> 4);
         uint4 A[6];
 #pragma unroll
         for (int p = 0; p < 6; ++p) A[p] = wp4[p * (PS / 4) + o];
-        // Re += Wr Xr + Wi Xi ;  Im += Wr Xi - Wi Xr
-        accR[t] = mfma_bf16x(A[0], Bv[0], accR[t]);
-        accR[t] = mfma_bf16x(A[3], Bv[3], accR[t]);
-        accI[t] = mfma_bf16x(A[0], Bv[3], accI[t]);
-        accI[t] = mfma_bf16x(negbf8(A[3]), Bv[0], accI[t]);
 #pragma unroll
-        for (int u = 0; u < 5; ++u) {
-          corR[t] = mfma_bf16x(A[PA[u]], Bv[PB[u]], corR[t]);
-          corR[t] = mfma_bf16x(A[3 + PA[u]], Bv[3 + PB[u]], corR[t]);
-          corI[t] = mfma_bf16x(A[PA[u]], Bv[3 + PB[u]], corI[t]);
-          corI[t] = mfma_bf16x(negbf8(A[3 + PA[u]]), Bv[PB[u]], corI[t]);
+        for (int w = 0; w < RTW; ++w) {
+          // Re += Wr Xr + Wi Xi ;  Im += Wr Xi - Wi Xr
+          accR[w][t] = mfma_bf16x(A[0], Bv[w][0], accR[w][t]);
+          accR[w][t] = mfma_bf16x(A[3], Bv[w][3], accR[w][t]);
+          accI[w][t] = mfma_bf16x(A[0], Bv[w][3], accI[w][t]);
+          accI[w][t] = mfma_bf16x(negbf8(A[3]), Bv[w][0], accI[w][t]);
+#pragma unroll
+          for (int u = 0; u < 5; ++u) {
+            corR[w][t] = mfma_bf16x(A[PA[u]], Bv[w][PB[u]], corR[w][t]);
+            corR[w][t] = mfma_bf16x(A[3 + PA[u]], Bv[w][3 + PB[u]], corR[w][t]);
+            corI[w][t] = mfma_bf16x(A[PA[u]], Bv[w][3 + PB[u]], corI[w][t]);
+            corI[w][t] = mfma_bf16x(negbf8(A[3 + PA[u]]), Bv[w][PB[u]], corI[w][t]);
+          }
         }
       }
     }
-    if (live) {
-      const long long rr = (long long)b * N + r;
+#pragma unroll
+    for (int w = 0; w < RTW; ++w) {
+      if (!live[w]) continue;
+      const long long rr = (long long)b * N + r[w];
 #pragma unroll
       for (int t = 0; t < ST; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int s = t * 16 + 4 * (lane >> 4) + i;
           if (s < S) {
-            const float re = accR[t][i] + corR[t][i], im = accI[t][i] + corI[t][i];
+            const float re = accR[w][t][i] + corR[w][t][i], im = accI[w][t][i] + corI[w][t][i];
             const long long o = ((long long)k * S + s) * d.R + rr;
             power[o] = re * re + im * im;
             if (yout) yout[o] = make_float2(re, im);
@@ -221,18 +239,18 @@ __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts
   }
 }
 
-template <int ST, int DP>
+template <int ST, int DP, int RTW>
 __global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ wts, const float2* __restrict__ snap,
                                                     float* __restrict__ power, float2* __restrict__ yout, Dims d) {
-  inner_system<ST, DP>(wts, snap, power, yout, d, blockIdx.x);
+  inner_system<ST, DP, RTW>(wts, snap, power, yout, d, blockIdx.x);
 }
 
-template <int ST, int DP>
+template <int ST, int DP, int RTW>
 __global__ __launch_bounds__(256) void inner_bf16_kernel(const float2* __restrict__ wts,
                                                          const float2* __restrict__ snap,
                                                          float* __restrict__ power, float2* __restrict__ yout,
                                                          Dims d) {
-  inner_bf16_system<ST, DP>(wts, snap, power, yout, d, blockIdx.x);
+  inner_bf16_system<ST, DP, RTW>(wts, snap, power, yout, d, blockIdx.x);
 }
 
 // Batched: one workgroup per system of every cube of the table.
@@ -261,29 +279,47 @@ hipError_t go_inner_batched(const ProbDesc* desc, int n, long long total, int ma
   return hipGetLastError();
 }
 
+// Range tiles per wave step: the tuned choice where given (1, 2 or 4;
+// 2 for the split-BF16 form at most), else 2 (FP32) and 1 (split BF16).
+template <int ST, int RTW>
+hipError_t go_inner_bf16_r(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
+                           hipStream_t st) {
+  dim3 grid(d.P * d.B), block(256);
+  if (d.D <= 32) hipLaunchKernelGGL((inner_bf16_kernel<ST, 32, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 64) hipLaunchKernelGGL((inner_bf16_kernel<ST, 64, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 96) hipLaunchKernelGGL((inner_bf16_kernel<ST, 96, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else hipLaunchKernelGGL((inner_bf16_kernel<ST, 128, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  return hipGetLastError();
+}
+
 template <int ST>
 hipError_t go_inner_bf16(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
+                         hipStream_t st, int rtw) {
+  return rtw == 2 ? go_inner_bf16_r<ST, 2>(d, w, snap, power, y, st) : go_inner_bf16_r<ST, 1>(d, w, snap, power, y, st);
+}
+
+template <int ST, int RTW>
+hipError_t go_inner_dp_r(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
                          hipStream_t st) {
   dim3 grid(d.P * d.B), block(256);
-  if (d.D <= 32) hipLaunchKernelGGL((inner_bf16_kernel<ST, 32>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 64) hipLaunchKernelGGL((inner_bf16_kernel<ST, 64>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 96) hipLaunchKernelGGL((inner_bf16_kernel<ST, 96>), grid, block, 0, st, w, snap, power, y, d);
-  else hipLaunchKernelGGL((inner_bf16_kernel<ST, 128>), grid, block, 0, st, w, snap, power, y, d);
+  if (d.D <= 16) hipLaunchKernelGGL((inner_kernel<ST, 16, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 32) hipLaunchKernelGGL((inner_kernel<ST, 32, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 48) hipLaunchKernelGGL((inner_kernel<ST, 48, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 64) hipLaunchKernelGGL((inner_kernel<ST, 64, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 96) hipLaunchKernelGGL((inner_kernel<ST, 96, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else if (d.D <= 128) hipLaunchKernelGGL((inner_kernel<ST, 128, RTW>), grid, block, 0, st, w, snap, power, y, d);
+  else hipLaunchKernelGGL((inner_kernel<ST, 192, RTW>), grid, block, 0, st, w, snap, power, y, d);
   return hipGetLastError();
 }
 
 template <int ST>
 hipError_t go_inner_dp(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
-                       hipStream_t st) {
-  dim3 grid(d.P * d.B), block(256);
-  if (d.D <= 16) hipLaunchKernelGGL((inner_kernel<ST, 16>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 32) hipLaunchKernelGGL((inner_kernel<ST, 32>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 48) hipLaunchKernelGGL((inner_kernel<ST, 48>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 64) hipLaunchKernelGGL((inner_kernel<ST, 64>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 96) hipLaunchKernelGGL((inner_kernel<ST, 96>), grid, block, 0, st, w, snap, power, y, d);
-  else if (d.D <= 128) hipLaunchKernelGGL((inner_kernel<ST, 128>), grid, block, 0, st, w, snap, power, y, d);
-  else hipLaunchKernelGGL((inner_kernel<ST, 192>), grid, block, 0, st, w, snap, power, y, d);
-  return hipGetLastError();
+                       hipStream_t st, int rtw) {
+  switch (rtw) {
+    case 1: return go_inner_dp_r<ST, 1>(d, w, snap, power, y, st);
+    case 4: return go_inner_dp_r<ST, 4>(d, w, snap, power, y, st);
+  }
+  return go_inner_dp_r<ST, 2>(d, w, snap, power, y, st);
 }
 
 }  // namespace
@@ -306,21 +342,21 @@ hipError_t launch_inner_batched(const ProbDesc* desc, int n, long long total_sys
 }
 
 hipError_t launch_inner(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
-                        hipStream_t st) {
+                        hipStream_t st, int rtw) {
   if (d.prec != STAP_PREC_FP32 && d.D <= 128) {
     switch ((d.S + 15) / 16) {
-      case 1: return go_inner_bf16<1>(d, w, snap, power, y, st);
-      case 2: return go_inner_bf16<2>(d, w, snap, power, y, st);
-      case 3: return go_inner_bf16<3>(d, w, snap, power, y, st);
-      case 4: return go_inner_bf16<4>(d, w, snap, power, y, st);
+      case 1: return go_inner_bf16<1>(d, w, snap, power, y, st, rtw);
+      case 2: return go_inner_bf16<2>(d, w, snap, power, y, st, rtw);
+      case 3: return go_inner_bf16<3>(d, w, snap, power, y, st, rtw);
+      case 4: return go_inner_bf16<4>(d, w, snap, power, y, st, rtw);
     }
     return hipErrorInvalidValue;
   }
   switch ((d.S + 15) / 16) {
-    case 1: return go_inner_dp<1>(d, w, snap, power, y, st);
-    case 2: return go_inner_dp<2>(d, w, snap, power, y, st);
-    case 3: return go_inner_dp<3>(d, w, snap, power, y, st);
-    case 4: return go_inner_dp<4>(d, w, snap, power, y, st);
+    case 1: return go_inner_dp<1>(d, w, snap, power, y, st, rtw);
+    case 2: return go_inner_dp<2>(d, w, snap, power, y, st, rtw);
+    case 3: return go_inner_dp<3>(d, w, snap, power, y, st, rtw);
+    case 4: return go_inner_dp<4>(d, w, snap, power, y, st, rtw);
   }
   return hipErrorInvalidValue;
 }

@@ -44,9 +44,10 @@ hipError_t launch_inner_batched(const ProbDesc* desc, int n, long long total_sys
 // X[P][D][R] <- windowed, time-staggered Doppler DFT of cube[C][P][R].
 hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipStream_t st);
 
-// cov[P][B][D][D] (loaded, full Hermitian) and delta[P][B] from X.
+// cov[P][B][D][D] (loaded, full Hermitian) and delta[P][B] from X; nw =
+// waves per system (0 = default of the DOF class).
 hipError_t launch_covariance(const Dims& d, const float2* snap, float2* cov, float* delta,
-                             hipStream_t st);
+                             hipStream_t st, int nw = 0);
 
 // W[P][B][S][D] and info[P][B] from loaded covariances and steering V[S][D].
 hipError_t launch_solve(const Dims& d, const float2* cov, const float2* steer, float2* w, int* info,
@@ -76,8 +77,9 @@ hipError_t launch_fused32(const Dims& d, const float2* snap, const float2* steer
 hipError_t launch_cfar(const Dims& d, int n_ref, int n_guard, double alpha, const float* power,
                        unsigned char* detect, hipStream_t st);
 
-// power[P][S][R] (and y if non-null) from W and X.
+// power[P][S][R] (and y if non-null) from W and X; rtw = range tiles per
+// wave step (0 = default).
 hipError_t launch_inner(const Dims& d, const float2* w, const float2* snap, float* power, float2* y,
-                        hipStream_t st);
+                        hipStream_t st, int rtw = 0);
 
 }  // namespace stap

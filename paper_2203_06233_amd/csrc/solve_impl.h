@@ -44,9 +44,11 @@ template <class K>
 struct SolveShared {
   float2 colL[2][K::DPX];  // column j below the pivot (zero at and above it)
   float2 colV[2][K::SPR];  // column j of the steering rows
-  float colP[2];           // the pivot M[j][j]
+  double colP[2];          // the pivot of column j in FP64
   float invd[K::DPX];
   float gam[K::SPR];
+  double d64[K::DPX];      // row sums of |L[i][k]|^2 over the finished columns, FP64
+  float rdiag[K::DPX];     // loaded diagonal R_L[i][i]
 };
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
@@ -155,7 +157,8 @@ __device__ __forceinline__ void sweep_fwd(float2 (&x)[K::NVS][K::NB], const floa
 // 16 at a time (a slab): the threads holding them publish u for the slab to
 // LDS as U[k][s], then each wave forms 16 x 16 output blocks (rows I) as
 // sum over K of R_L[I][K] U[K] with v_mfma_f64_16x16x4 (four real products
-// per complex one; FP32 operands converted exactly, FP64 accumulation), takes
+// per complex one: three real products in the Gauss form; FP32 operands
+// converted exactly, FP64 accumulation), takes
 // r = v - R_L u in FP64, rounds it to FP32 and hands it back through the same
 // slab.  FP64 MFMA lane layout (lane l, m = l % 16, q = l / 16): A operand
 // A[m][q], B operand B[q][m], result register i holds D[q + 4i][m] (rows
@@ -197,7 +200,9 @@ __device__ __forceinline__ void residual_mfma(const RSrc& src, const float2* Rp,
     for (int ii = 0; ii < NI; ++ii) {
       const int I = wave + NW * ii;
       if (I < NB) {
-        doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+        // three real products per complex one (a1 = ar ur, a2 = ai ui,
+        // a3 = (ar + ai)(ur + ui); Re = a1 - a2, Im = a3 - a1 - a2)
+        doublex4 a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
         const int m = 16 * I + m16;
 #pragma unroll 1
         for (int kb = 0; kb < NB; ++kb) {
@@ -207,12 +212,12 @@ __device__ __forceinline__ void residual_mfma(const RSrc& src, const float2* Rp,
             const float2 r = relem(m, k);
             const float2 u = slab[k * 16 + m16];
             const double ar = r.x, ai = r.y, ur = u.x, ui = u.y;
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ur, cr, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, ui, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ui, ci, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ur, ci, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, ur, a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, ui, a2, 0, 0, 0);
+            a3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, ur + ui, a3, 0, 0, 0);
           }
         }
+        const doublex4 cr = a1 - a2, ci = a3 - a1 - a2;
         const int s = 16 * N + m16;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -276,6 +281,18 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
       vm[a][b] = (s < S && k < D) ? conjf2(steer[s * D + k]) : make_float2(0.f, 0.f);
     }
 
+  // The pivots are taken in FP64: d64[i] sums |L[i][k]|^2 (the FP32 factor
+  // entries, squared and added in FP64) over the finished columns k, and the
+  // pivot of column j is rdiag[j] - d64[j] in FP64, tested > 0 in FP64 and
+  // used rounded to FP32.  Row i's sum is updated by the one thread that
+  // finalises L[i][j] and read by the one that publishes column j + 1, in the
+  // same wave and in that order.
+  for (int i = tid; i < K::DPX; i += NT) {
+    sh.d64[i] = 0.0;
+    sh.rdiag[i] = i < D ? src.lower(i, i).x : 1.f;
+  }
+  __syncthreads();
+
   // Column j is published already masked: colL holds rows i > j (zero at
   // and above the pivot), colP the pivot.  Every thread then forms
   // li = c_i / piv for its rows and lk = c_k for its columns with no
@@ -290,7 +307,7 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
       for (int a = a0; a < NA; ++a) {
         const int i = ty + TY * a;
         sh.colL[0][i] = (i > j0) ? lm[a][jb] : make_float2(0.f, 0.f);
-        if (i == j0) sh.colP[0] = lm[a][jb].x;
+        if (i == j0) sh.colP[0] = (double)sh.rdiag[j0] - sh.d64[j0];
       }
 #pragma unroll
       for (int a = 0; a < NVS; ++a) sh.colV[0][ty + TY * a] = vm[a][jb];
@@ -300,11 +317,12 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
     for (int jt = 0; jt < jend; ++jt) {
       const int j = j0 + jt;
       const int buf = jt & 1;
-      const float piv = sh.colP[buf];
-      if (!(piv > 0.f)) {
+      const double piv64 = sh.colP[buf];
+      if (!(piv64 > 0.0)) {
         fail = j + 1;
         break;
       }
+      const float piv = (float)piv64;
       const float dj = sqrtf(piv), rs = 1.f / dj, ip = rs * rs;
       float2 li[NA], lk[NB], lv[NVS];
 #pragma unroll
@@ -325,8 +343,13 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
         for (int a = a0; a < NA; ++a) {
           const int i = ty + TY * a;
           const float2 c = lm[a][jb];
-          if (i > j) lm[a][jb] = make_float2(c.x * rs, c.y * rs);
-          else if (i == j) lm[a][jb] = make_float2(dj, 0.f);
+          if (i > j) {
+            const float2 l = make_float2(c.x * rs, c.y * rs);
+            lm[a][jb] = l;
+            sh.d64[i] += (double)l.x * (double)l.x + (double)l.y * (double)l.y;
+          } else if (i == j) {
+            lm[a][jb] = make_float2(dj, 0.f);
+          }
         }
 #pragma unroll
         for (int a = 0; a < NVS; ++a) vm[a][jb] = make_float2(vm[a][jb].x * rs, vm[a][jb].y * rs);
@@ -345,7 +368,7 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
         for (int a = a0; a < NA; ++a) {
           const int i = ty + TY * a;
           sh.colL[buf ^ 1][i] = (i > j + 1) ? lm[a][jb] : make_float2(0.f, 0.f);
-          if (i == j + 1) sh.colP[buf ^ 1] = lm[a][jb].x;
+          if (i == j + 1) sh.colP[buf ^ 1] = (double)sh.rdiag[j + 1] - sh.d64[j + 1];
         }
 #pragma unroll
         for (int a = 0; a < NVS; ++a) sh.colV[buf ^ 1][ty + TY * a] = vm[a][jb];

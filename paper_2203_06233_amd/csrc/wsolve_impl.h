@@ -147,24 +147,31 @@ __device__ __forceinline__ void step_work(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[
 // instruction stream interleaves the serial VALU work of diagonal block
 // J+1 with independent matrix-core products.
 template <int NB, int NS, int J, int j>
-__device__ __forceinline__ void diag_cols_work(Frag& A, Frag& X, int m, float& rsm, int& fail,
+__device__ __forceinline__ void diag_cols_work(Frag& A, Frag& X, int m, float& rsm, int& fail, double& p64,
                                                Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB]) {
   constexpr int C = StepWork<NB, NS, J>::COUNT;
-  diag_col<j>(A, X, m, rsm, fail);
+  diag_col<j>(A, X, m, rsm, fail, p64);
   step_work<NB, NS, J, j * C / 16, (j + 1) * C / 16>(L, M);
-  if constexpr (j < 15) diag_cols_work<NB, NS, J, j + 1>(A, X, m, rsm, fail, L, M);
+  if constexpr (j < 15) diag_cols_work<NB, NS, J, j + 1>(A, X, m, rsm, fail, p64, L, M);
 }
 
 // Factorisation step J (diagonal block J already holds Linv_JJ): panel,
 // the update and factorisation of diagonal block J+1 interleaved with the
-// remaining updates of the step, then step J+1.
+// remaining updates of the step, then step J+1.  d64 (LDS) collects the
+// FP64 row sums of |L|^2 over the finished block columns and rdiag holds
+// the loaded diagonal: the FP64 pivots of block J+1 start from their
+// difference.
 template <int NB, int NS, int J>
-__device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB], int& fail) {
+__device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB], int& fail, double* d64,
+                                          const float* rdiag) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int I = J + 1; I < NB; ++I) {
     Acc x = acc_zero();
     pqh<false>(x, L[tri(I, J)], L[tri(J, J)]);
     L[tri(I, J)] = x;
+    const double pn = frag_row_norm2(x);
+    if (lane < 16) d64[16 * I + lane] += pn;
   }
 #pragma unroll
   for (int N = 0; N < NS; ++N) {
@@ -180,22 +187,26 @@ __device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[
     for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
     int f = 0;
     float rsm = 1.f;
-    diag_cols_work<NB, NS, J, 0>(A, X, m, rsm, f, L, M);
+    double p64 = (double)rdiag[16 * (J + 1) + m] - d64[16 * (J + 1) + m];
+    diag_cols_work<NB, NS, J, 0>(A, X, m, rsm, f, p64, L, M);
 #pragma unroll
     for (int i = 0; i < 4; ++i) X.v[i] = make_float2(X.v[i].x * rsm, X.v[i].y * rsm);
     fail = (fail == 0 && f != 0) ? 16 * (J + 1) + f : fail;
     L[tri(J + 1, J + 1)] = to_acc(X);
-    fact_step<NB, NS, J + 1>(L, M, fail);
+    fact_step<NB, NS, J + 1>(L, M, fail, d64, rdiag);
   }
 }
 
 // LDS of one system: transpose slots, then (REFINE) the packed lower
-// triangle of R_L, row r at offset r (r + 1) / 2.
+// triangle of R_L, row r at offset r (r + 1) / 2, then the FP64 row sums of
+// |L|^2 (16 NB doubles) and the loaded diagonal (16 NB floats) for the
+// pivots.
 template <int NB, bool REFINE>
 struct WsLds {
   static constexpr int SLOTS = REFINE ? 1 : NB;
   static constexpr int PACK = REFINE ? 16 * NB * (16 * NB + 1) / 2 : 0;
-  static constexpr int COMPLEX = SLOTS * 256 + PACK;
+  static constexpr int PIV = 16 * NB + 8 * NB;  // in complex (8-byte) units
+  static constexpr int COMPLEX = SLOTS * 256 + PACK + PIV;
 };
 
 // Solve one system: R is its loaded covariance, full Hermitian [D][D]
@@ -215,6 +226,9 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
   const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
   float2* tb = lds;
   float2* Rp = lds + LY::SLOTS * 256;
+  double* d64 = reinterpret_cast<double*>(Rp + LY::PACK);
+  float* rdiag = reinterpret_cast<float*>(d64 + 16 * NB);
+  for (int r = lane; r < 16 * NB; r += 64) d64[r] = 0.0;
 
   Acc L[NL], M[NS * NB];
 #pragma unroll
@@ -230,6 +244,7 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
         a.re[i] = v.x;
         a.im[i] = v.y;
         if (REFINE && c <= r && r < D) Rp[r * (r + 1) / 2 + c] = v;
+        if (I == J && c == r) rdiag[r] = v.x;
       }
       L[tri(I, J)] = a;
     }
@@ -255,11 +270,11 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
   int fail = 0;
   {
     Frag A = to_frag(L[0]), X;
-    const int f = diag_factor_inv(A, X);
+    const int f = diag_factor_inv(A, X, (double)frag_diag(A));
     fail = f != 0 ? f : 0;
     L[0] = to_acc(X);
   }
-  fact_step<NB, NS, 0>(L, M, fail);
+  fact_step<NB, NS, 0>(L, M, fail, d64, rdiag);
   if (fail) {
     for (int e = lane; e < S * D; e += 64) W[e] = make_float2(0.f, 0.f);
     if (lane == 0 && info) *info = fail;
@@ -312,7 +327,10 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
         const int s = 16 * N + m;
 #pragma unroll
         for (int I = 0; I < NB; ++I) {
-          doublex4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+          // three real products per complex one: a1 = sum qr pr,
+          // a2 = sum qi pi, a3 = sum (qr + qi)(pr + pi); Re = a1 - a2,
+          // Im = a3 - a1 - a2 (the FP64 sums of FP32 values are exact)
+          doublex4 a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
           const int c = 16 * I + m;
           // operands of block row J: R[16J + 4q + s4][c] and the lane's
           // Z_NJ[m][4q + s4]; fetched one step ahead of their MFMAs
@@ -339,10 +357,9 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
               const double qr = rv[s4].x, qi = rv[s4].y, pr = z[s4].x, pi = z[s4].y;
-              cr = mfma64(qr, pr, cr);
-              cr = mfma64(-qi, pi, cr);
-              ci = mfma64(qr, pi, ci);
-              ci = mfma64(qi, pr, ci);
+              a1 = mfma64(qr, pr, a1);
+              a2 = mfma64(qi, pi, a2);
+              a3 = mfma64(qr + qi, pr + pi, a3);
             }
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
@@ -350,6 +367,7 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
               z[s4] = zn[s4];
             }
           }
+          const doublex4 cr = a1 - a2, ci = a3 - a1 - a2;
           __syncthreads();  // earlier reads of tb are done
 #pragma unroll
           for (int i = 0; i < 4; ++i) {

@@ -5,8 +5,11 @@ every candidate variant of the fused covariance->solve kernel (the
 column-sweep solve on a 16 x 16 or 32 x 16 thread grid per system, the
 blocked matrix-core solve with 4 or 8 waves, or the stage covariance
 followed by the one-wave solve), keeps the fastest by HIP-event time, and
-stores the choice in a JSON cache keyed by GPU architecture, DOF class,
-steering class, precision and refinement.  The binding applies the cache
+stores the choice in a JSON cache keyed by GPU architecture, kernel kind,
+DOF class, steering class, precision and refinement.  It then times the
+stage covariance kernel under each wave count per system and the inner
+products under each number of range tiles per wave step (kinds "cov" and
+"inner"), which must reproduce the default bit for bit.  The binding applies the cache
 (``tune_cache.json`` beside this file, or ``$STAP_TUNE_CACHE``) at import.
 
     python -m paper_2203_06233_amd.tune [--workload large] [--reps 10]
@@ -43,7 +46,19 @@ def arch() -> str:
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
-KINDS = {"fused": 0, "stage": 1}
+KINDS = {"fused": 0, "stage": 1, "cov": 2, "inner": 3}
+
+
+def kernel_candidates(kind, dof, precision):
+    """Variants of the covariance (waves per system) and inner-product (range
+    tiles per wave step) kernels for a DOF class; 0 is the built-in default."""
+    if kind == KINDS["cov"]:
+        if dof <= 32 or dof > 128:
+            return [0]
+        return [0, 4, 8] if dof <= 64 else [0, 4, 16] if dof <= 96 else [0, 16]
+    if kind == KINDS["inner"]:
+        return [0, 1, 2] if precision != "fp32" and dof <= 128 else [0, 1, 2, 4]
+    return [0]
 
 
 def kind_of(wl, precision):
@@ -127,6 +142,55 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
     return best, times
 
 
+def tune_kernel(wl, precision, refine, kind, reps=10, warmup=3):
+    """Time stap_covariance (kind 2) or stap_inner_products (kind 3) on the
+    workload's snapshots under each candidate variant; the outputs must agree
+    bit for bit (the variants only regroup the same arithmetic)."""
+    import torch
+
+    import synth
+    from paper_2203_06233_amd import stap
+
+    dev = torch.device("cuda:0")
+    cube = torch.from_numpy(synth.make_cube(wl)).to(dev)
+    V = torch.from_numpy(synth.steering(wl)).to(dev)
+    prob = stap.problem(wl.n_chan, wl.n_pulse, wl.n_range, wl.tdof, wl.n_block, wl.n_steer,
+                        load_eps=wl.load_eps, precision=precision, refine_steps=refine)
+    snap = stap.doppler(prob, cube)
+    if kind == KINDS["cov"]:
+        cov, delta = stap.covariance(prob, snap)
+        call = lambda: stap.covariance(prob, snap, cov, delta)
+        out = lambda: cov
+    else:
+        cov, _ = stap.covariance(prob, snap)
+        w, _ = stap.solve_weights(prob, cov, V)
+        del cov
+        power = stap.inner_products(prob, w, snap)
+        call = lambda: stap.inner_products(prob, w, snap, power)
+        out = lambda: power
+    times, ref = {}, None
+    for v in kernel_candidates(kind, wl.dof, precision):
+        stap.tune_set(wl.dof, wl.n_steer, precision, refine, v, kind=kind)
+        for _ in range(warmup):
+            call()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            call()
+        e1.record(st)
+        torch.cuda.synchronize()
+        times[v] = e0.elapsed_time(e1) / reps
+        o = out().cpu()
+        if ref is None:
+            ref = o
+        elif not torch.equal(o, ref):
+            raise RuntimeError(f"kind {kind} variant {v} does not reproduce the default bit for bit")
+    best = min(times, key=times.get)
+    stap.tune_set(wl.dof, wl.n_steer, precision, refine, best, kind=kind)
+    return best, times
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="all", choices=["all", "small", "medium", "large", "xlarge", "uneven"])
@@ -157,6 +221,16 @@ def main():
             best, times = tune_workload(wl, precision, refine, reps=args.reps)
             cache[k] = {"variant": best, "ms": {str(v): t for v, t in times.items()}, "workload": wl.name}
             print(json.dumps({"key": k, **cache[k]}), flush=True)
+            for kname in ("cov", "inner"):
+                kk = key(a, dc, sc, precision, refine, KINDS[kname])
+                if kk in seen:
+                    continue
+                seen.add(kk)
+                if len(kernel_candidates(KINDS[kname], wl.dof, precision)) < 2:
+                    continue
+                best, times = tune_kernel(wl, precision, refine, KINDS[kname], reps=args.reps)
+                cache[kk] = {"variant": best, "ms": {str(v): t for v, t in times.items()}, "workload": wl.name}
+                print(json.dumps({"key": kk, **cache[kk]}), flush=True)
     with open(args.out, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     print(f"wrote {args.out}")

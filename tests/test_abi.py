@@ -210,7 +210,6 @@ def test_tuning_table(binding):
     finally:
         binding.tune_set(96, 32, "bf16", 1, saved)
     assert lib.stap_tune_set(0, 96, 32, 1, 1, 24) == -1
-    assert lib.stap_tune_set(2, 96, 32, 1, 1, 16) == -1
     assert lib.stap_tune_set(1, 96, 32, 1, 0, 8) == 0 and lib.stap_tune_get(1, 96, 32, 1, 0) == 8
     assert lib.stap_tune_set(1, 96, 32, 1, 0, 0) == 0
     assert lib.stap_tune_set(0, 200, 32, 1, 1, 16) == -1
@@ -221,6 +220,16 @@ def test_tuning_table(binding):
         assert lib.stap_tune_set(kind, 96, 32, 1, 0, 1) == 0 and lib.stap_tune_get(kind, 96, 32, 1, 0) == 1
         assert lib.stap_tune_set(kind, 96, 32, 1, 0, old) == 0
     assert lib.stap_tune_set(0, 96, 32, 1, 0, 2) == -1
+    # kind 2: waves per system of the stage covariance; kind 3: range tiles
+    # per wave step of the inner products
+    for kind, good, bad in ((2, (0, 4, 8, 16), (1, 2, 32)), (3, (0, 1, 2, 4), (8, 16, 3))):
+        old = lib.stap_tune_get(kind, 96, 32, 1, 1)
+        for v in good:
+            assert lib.stap_tune_set(kind, 96, 32, 1, 1, v) == 0 and lib.stap_tune_get(kind, 96, 32, 1, 1) == v
+        for v in bad:
+            assert lib.stap_tune_set(kind, 96, 32, 1, 1, v) == -1
+        assert lib.stap_tune_set(kind, 96, 32, 1, 1, old) == 0
+    assert lib.stap_tune_set(4, 96, 32, 1, 1, 0) == -1
 
 
 def test_tuner_candidates():
@@ -231,6 +240,19 @@ def test_tuner_candidates():
     assert 1 not in tune.candidates(96, 0, 0, 33)  # S > 32
     assert tune.candidates(192, 1, 1, 64) == [0, 8]
     assert 32 not in tune.candidates(32, 0)  # the 32-row grid needs D > 32
+
+
+def test_kernel_tuning_candidates():
+    """Covariance wave counts and inner-product tile counts the tuner tries
+    per DOF class (0 = the default)."""
+    from paper_2203_06233_amd import tune
+    assert tune.kernel_candidates(2, 96, "bf16") == [0, 4, 16]
+    assert tune.kernel_candidates(2, 48, "fp32") == [0, 4, 8]
+    assert tune.kernel_candidates(2, 128, "fp32") == [0, 16]
+    assert tune.kernel_candidates(2, 24, "fp32") == [0] and tune.kernel_candidates(2, 192, "fp8") == [0]
+    assert tune.kernel_candidates(3, 96, "bf16") == [0, 1, 2]
+    assert tune.kernel_candidates(3, 96, "fp32") == [0, 1, 2, 4]
+    assert tune.kernel_candidates(3, 192, "fp8") == [0, 1, 2, 4]  # D > 128 takes the FP32 form
 
 
 def test_workspace_size_formula(binding):

@@ -547,6 +547,44 @@ def check_doppler_p100(orc=stap):
         assert np.all(np.abs(Xt[k0] - 48.5) < 1e-10)
 
 
+def near_singular_cases():
+    """The two matrices of golden/near_singular_pivots.json as complex64
+    arrays, with the sign of their last pivot from exact rational
+    arithmetic."""
+    from fractions import Fraction
+    g = json.load(open(os.path.join(GOLDEN, "near_singular_pivots.json")))
+    out = []
+    for case in g["cases"]:
+        a = [np.float32(1.0 + k * 2.0 ** -23) for k in case["k"]]
+        n = len(a)
+        R = np.eye(n + 1, dtype=np.complex64)
+        R[n, :n] = a
+        R[:n, n] = a
+        R[n, n] = np.float32(case["r_last"])
+        exact = Fraction(float(R[n, n].real)) - sum(Fraction(float(x)) ** 2 for x in a)
+        out.append((R, exact))
+    return out
+
+
+def check_info_near_singular(orc=stap):
+    """Pivots that FP32 accumulation gets wrong: the exact last pivot (rational
+    arithmetic) is positive for one matrix and negative for the other, and
+    the oracle's status follows it (0, and 20 = the 1-based index of the last
+    pivot).  A running FP32 update of the last diagonal (each fused
+    multiply-add rounded to FP32) ends with the opposite sign in both cases,
+    which is why the pivot test is taken in FP64."""
+    for R, exact in near_singular_cases():
+        n = R.shape[0] - 1
+        want = 0 if exact > 0 else n + 1
+        assert exact != 0
+        _, info = orc.cholesky_info(R.astype(np.complex128))
+        assert info == want, (info, want)
+        A = np.float32(R[n, n].real)
+        for k in range(n):
+            A = np.float32(float(A) - float(R[n, k].real) ** 2)
+        assert (float(A) > 0) != (exact > 0)
+
+
 METRIC_CHECKS = [check_rel_err_known_norms, check_per_system_rel_err_block_diagonal,
                  check_sinr_closed_form, check_sinr_loss_closed_form]
 
@@ -558,7 +596,8 @@ CHECKS = [check_window_library_and_sums, check_doppler_brute_force, check_dopple
           check_doppler_relative_brute_force, check_relative_chain_equivalence,
           check_offbin_target_per_bin, check_training_cells, check_covariance_excluded_brute_force,
           check_excluded_cut_no_self_nulling, check_run_block_matches_excluded,
-          check_subarray_brute_force, check_subarray_plane_wave, check_doppler_p100]
+          check_subarray_brute_force, check_subarray_plane_wave, check_doppler_p100,
+          check_info_near_singular]
 CHAIN_CHECKS = [check_block_sum_and_cell_bound, check_target_recovered, check_sinr_loss,
                 check_block_sampling]
 

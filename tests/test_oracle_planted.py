@@ -155,6 +155,20 @@ def subarray(cube, n_sub):
     x = cube.astype(np.complex128)
     return x.reshape(C // n_sub, n_sub, P, R).mean(axis=1)
 """,
+    "pivot_test_in_fp32": """
+def cholesky_info(A):
+    D = A.shape[0]
+    L = np.zeros_like(A, dtype=np.complex128)
+    for j in range(D):
+        piv = np.float32(np.real(A[j, j]))
+        for k in range(j):
+            piv = np.float32(float(piv) - float(np.abs(L[j, k]) ** 2))
+        if not (piv > 0.0) or not np.isfinite(piv):
+            return L, j + 1
+        L[j, j] = np.sqrt(float(piv))
+        L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ np.conj(L[j, :j])) / L[j, j]
+    return L, 0
+""",
 }
 
 
