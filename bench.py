@@ -369,7 +369,23 @@ def main():
             prun.run([pcube], [pv], powers=ppow)
         torch.cuda.synchronize()
         pms = (time.perf_counter() - t) / psteps * 1e3
+        # host-to-device rate from pinned memory, for the rate of a cube that
+        # starts in host memory (copies overlapped with the previous cube's
+        # processing, the PCIe-inclusive rate is the smaller of the two)
+        hbuf = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+        dbuf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dbuf.copy_(hbuf, non_blocking=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            dbuf.copy_(hbuf, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d = 3 * (1 << 30) / (time.perf_counter() - t)
+        del hbuf, dbuf
+        cube_bytes = wp.n_pulse * wp.n_chan * wp.n_range * 8
         paper = dict(workload=wp.name, layout="pulses x channels x samples (strides)", subarray=wp.n_sub,
+                     h2d_GBps=h2d / 1e9,
+                     pcie_inclusive_cubes_per_s=min(1e3 / pms, h2d / cube_bytes),
                      D=wp.dof, B=wp.n_block, N=wp.n_cell, S=wp.n_steer, precision=args.precision,
                      refine_steps=args.refine, ms_per_cube=pms, cubes_per_s=1e3 / pms,
                      real_time_cubes_per_s=33.3, value=wp.cells_dof / (pms * 1e-3), steps=psteps,

@@ -209,10 +209,13 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
  * All problems must share precision and refine_steps.  With n_probs > 1 and
  * every cube fused-eligible (D <= 128, FP32 or BF16) the batch runs as one
  * Doppler launch per pulse count, one persistent covariance->solve launch
- * over every (cube, bin, block) system ordered by cost, and one
- * inner-product launch; the problem table (n_probs * 128 bytes) is copied
- * from the host into the workspace and the launch chain is replayed from a
- * cached hipGraph.  A single cube runs Doppler, the fused covariance->solve
+ * whose workgroups take the (cube, bin, block) systems, most expensive
+ * first, from a device work queue, and one inner-product launch; the problem
+ * table (136 bytes per cube, plus the queue counter) is written into the
+ * workspace by a kernel that carries it in its arguments, and the launch
+ * chain is replayed from a cached hipGraph (a stream that is being captured
+ * gets the launches directly, table kernel included).  Batches with a cube
+ * that is not fused-eligible run cube by cube.  A single cube runs Doppler, the fused covariance->solve
  * (or, where the tuning table selects kind-0 variant 1 or the shape is not
  * fused-eligible, the stage covariance and a stage solve), and the inner
  * products.  Calls that overlap on one workspace race. */

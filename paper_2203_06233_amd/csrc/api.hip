@@ -174,7 +174,9 @@ Parts parts_of(const stap_problem* q) {
   p.info = up(P * B * 4);
   return p;
 }
-size_t table_bytes(int n) { return up((size_t)n * sizeof(stap::ProbDesc)); }
+// The problem table of a batch, then the 8-byte work-queue counter of the
+// persistent covariance -> solve kernel.
+size_t table_bytes(int n) { return up((size_t)n * sizeof(stap::ProbDesc) + sizeof(unsigned long long)); }
 
 // Per-system cost used to order a batch (largest first).
 double system_cost(const Dims& d) {
@@ -226,20 +228,24 @@ struct TableChunk {
 };
 static_assert(sizeof(stap::ProbDesc) % 8 == 0, "table entries are copied as 8-byte words");
 
-__global__ void table_kernel(stap::ProbDesc* __restrict__ table, TableChunk c) {
+// The first chunk's launch also resets the work-queue counter (a kernel
+// store, so a captured graph resets it on every replay).
+__global__ void table_kernel(stap::ProbDesc* __restrict__ table, TableChunk c, unsigned long long* queue) {
   const int words = c.n * (int)(sizeof(stap::ProbDesc) / 8);
   const unsigned long long* src = reinterpret_cast<const unsigned long long*>(c.d);
   unsigned long long* dst = reinterpret_cast<unsigned long long*>(table + c.first);
   for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  if (c.first == 0 && threadIdx.x == 0) *queue = 0ULL;
 }
 
-hipError_t upload_table(stap::ProbDesc* table, const std::vector<stap::ProbDesc>& desc, hipStream_t st) {
+hipError_t upload_table(stap::ProbDesc* table, const std::vector<stap::ProbDesc>& desc, unsigned long long* queue,
+                        hipStream_t st) {
   for (int first = 0; first < (int)desc.size(); first += kTableChunk) {
     TableChunk c;
     c.first = first;
     c.n = std::min(kTableChunk, (int)desc.size() - first);
     for (int i = 0; i < c.n; ++i) c.d[i] = desc[first + i];
-    hipLaunchKernelGGL(table_kernel, dim3(1), dim3(256), 0, st, table, c);
+    hipLaunchKernelGGL(table_kernel, dim3(1), dim3(256), 0, st, table, c, queue);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -280,6 +286,7 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
                      const stap_cf32* const* steers, float* const* powers, stap_cf32* const* weights,
                      int32_t* const* info, char* const ws0, hipStream_t st, bool graphs_ok) {
   stap::ProbDesc* table = reinterpret_cast<stap::ProbDesc*>(ws0);
+  unsigned long long* queue = reinterpret_cast<unsigned long long*>(ws0 + (size_t)n_probs * sizeof(stap::ProbDesc));
   char* ws = ws0 + table_bytes(n_probs);
   std::vector<stap::ProbDesc> desc(n_probs);
   bool all_fused = true;
@@ -373,12 +380,12 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
       hipError_t e = stap::launch_doppler_batched(x.second, table, x.first, x.first.tile_begin[x.first.n], s);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = stap::launch_fused_batched(table, n_probs, total, max_dof, max_steer, prec, refine, ty, s);
+    hipError_t e = stap::launch_fused_batched(table, n_probs, total, max_dof, max_steer, prec, refine, ty, s, queue);
     if (e != hipSuccess) return e;
     return stap::launch_inner_batched(table, n_probs, total, max_dof, max_steer, prec, s);
   };
 
-  if (upload_table(table, desc, st) != hipSuccess) return STAP_ERR_HIP;
+  if (upload_table(table, desc, queue, st) != hipSuccess) return STAP_ERR_HIP;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) return STAP_ERR_HIP;
   if (!graphs_ok || !g_use_graphs || cap != hipStreamCaptureStatusNone) return hip_status(enqueue(st));

@@ -30,15 +30,17 @@ hipError_t go1(const Dims& d, const float2* snap, const float2* steer, float2* w
 }
 
 template <int NB, int NS, int NW, int MODE>
-hipError_t gob(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st) {
+hipError_t gob(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st, unsigned long long* queue) {
   constexpr int L = nsl(NB, NW), M = nsm(NB, NS, NW);
   // enough workgroups to fill every CU a few times over, never more than systems
   const long long want = 256LL * (NW == 4 ? 4 : 2);
   const dim3 grid((unsigned)(total < want ? total : want)), block(64 * NW);
   if (refine == 0)
-    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, false>), grid, block, 0, st, desc, n, total);
+    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, false>), grid, block, 0, st, desc, n, total,
+                       queue);
   else
-    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, true>), grid, block, 0, st, desc, n, total);
+    hipLaunchKernelGGL((bfused_batched_kernel<NB, NS, L, M, NW, MODE, true>), grid, block, 0, st, desc, n, total,
+                       queue);
   return hipGetLastError();
 }
 
@@ -77,9 +79,10 @@ hipError_t single(const Dims& d, const float2* snap, const float2* steer, float2
 
 template <int MODE>
 hipError_t batched(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer, int refine, int waves,
-                   hipStream_t st) {
+                   hipStream_t st, unsigned long long* queue) {
   return pick<MODE>(max_dof, max_steer, waves, [&](auto nb, auto ns, auto nw) {
-    return gob<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(desc, n, total, refine, st);
+    return gob<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(desc, n, total, refine, st,
+                                                                                   queue);
   });
 }
 

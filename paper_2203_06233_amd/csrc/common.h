@@ -239,7 +239,11 @@ __device__ __forceinline__ void fft_inreg(float2 (&v)[M]) {
         const int idx = j * (64 / (2 * half));
         const float2 w = make_float2(tw.c[idx], -tw.s[idx]);
         const float2 a = v[start + j];
-        const float2 b = (j == 0) ? v[start + j + half] : cmul(v[start + j + half], w);
+        const float2 c = v[start + j + half];
+        // idx 0 and 16 are the twiddles 1 and -i (a swap and a sign, exact);
+        // products with 0 and +-1 are not folded under IEEE rules, so they
+        // are taken apart here (idx is a constant after unrolling)
+        const float2 b = (idx == 0) ? c : (idx == 16) ? make_float2(c.y, -c.x) : cmul(c, w);
         v[start + j] = cadd(a, b);
         v[start + j + half] = csub(a, b);
       }

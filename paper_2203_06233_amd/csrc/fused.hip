@@ -25,29 +25,30 @@ hipError_t go16_d(const Dims& d, const float2* snap, const float2* steer, float2
 }
 
 template <int NB, int MODE>
-hipError_t gob16_s(const ProbDesc* desc, int n, long long total, int max_steer, int refine, hipStream_t st) {
-  if (max_steer <= 16) return go_fused_batched<16, NB, NB, 1, MODE>(desc, n, total, refine, st);
-  if (max_steer <= 32) return go_fused_batched<16, NB, NB, 2, MODE>(desc, n, total, refine, st);
-  return go_fused_batched<16, NB, NB, 4, MODE>(desc, n, total, refine, st);
+hipError_t gob16_s(const ProbDesc* desc, int n, long long total, int max_steer, int refine, hipStream_t st,
+                    unsigned long long* queue) {
+  if (max_steer <= 16) return go_fused_batched<16, NB, NB, 1, MODE>(desc, n, total, refine, st, queue);
+  if (max_steer <= 32) return go_fused_batched<16, NB, NB, 2, MODE>(desc, n, total, refine, st, queue);
+  return go_fused_batched<16, NB, NB, 4, MODE>(desc, n, total, refine, st, queue);
 }
 
 template <int MODE>
 hipError_t gob16_d(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer, int refine,
-                   hipStream_t st) {
-  if (max_dof <= 16) return gob16_s<1, MODE>(desc, n, total, max_steer, refine, st);
-  if (max_dof <= 32) return gob16_s<2, MODE>(desc, n, total, max_steer, refine, st);
-  if (max_dof <= 48) return gob16_s<3, MODE>(desc, n, total, max_steer, refine, st);
-  if (max_dof <= 64) return gob16_s<4, MODE>(desc, n, total, max_steer, refine, st);
-  if (max_dof <= 96) return gob16_s<6, MODE>(desc, n, total, max_steer, refine, st);
-  return gob16_s<8, MODE>(desc, n, total, max_steer, refine, st);
+                   hipStream_t st, unsigned long long* queue) {
+  if (max_dof <= 16) return gob16_s<1, MODE>(desc, n, total, max_steer, refine, st, queue);
+  if (max_dof <= 32) return gob16_s<2, MODE>(desc, n, total, max_steer, refine, st, queue);
+  if (max_dof <= 48) return gob16_s<3, MODE>(desc, n, total, max_steer, refine, st, queue);
+  if (max_dof <= 64) return gob16_s<4, MODE>(desc, n, total, max_steer, refine, st, queue);
+  if (max_dof <= 96) return gob16_s<6, MODE>(desc, n, total, max_steer, refine, st, queue);
+  return gob16_s<8, MODE>(desc, n, total, max_steer, refine, st, queue);
 }
 
 }  // namespace
 
 hipError_t launch_fused_batched16(const ProbDesc* desc, int n, long long total, int max_dof, int max_steer,
-                                  int prec, int refine, hipStream_t st) {
-  return prec == STAP_PREC_FP32 ? gob16_d<0>(desc, n, total, max_dof, max_steer, refine, st)
-                                : gob16_d<1>(desc, n, total, max_dof, max_steer, refine, st);
+                                  int prec, int refine, hipStream_t st, unsigned long long* queue) {
+  return prec == STAP_PREC_FP32 ? gob16_d<0>(desc, n, total, max_dof, max_steer, refine, st, queue)
+                                : gob16_d<1>(desc, n, total, max_dof, max_steer, refine, st, queue);
 }
 
 hipError_t launch_fused16(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,

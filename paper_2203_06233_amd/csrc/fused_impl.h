@@ -63,13 +63,25 @@ __global__ __launch_bounds__(16 * TY) void fused_kernel(const float2* __restrict
   fused_system<TY, NA, NB, NVS, MODE, REFINE>(snap, steer, wout, info_out, d, blockIdx.x);
 }
 
-// Persistent: a grid-stride loop over the systems of every cube of the
-// table.  Cubes are ordered by cost (largest first), so the most expensive
-// systems are handed out first.
+// Persistent workgroups take the next system from a device work queue: one
+// 64-bit counter (reset by the launch that writes the problem table) that
+// each workgroup advances atomically when it finishes a system.  Cubes are
+// ordered by cost (largest first), so the most expensive systems are handed
+// out first and the cheap ones fill in behind them.  Every workgroup leaves
+// when the counter has passed the last system.
+__device__ __forceinline__ long long next_system(unsigned long long* queue, long long* slot) {
+  if (threadIdx.x == 0) *slot = (long long)atomicAdd(queue, 1ULL);
+  __syncthreads();
+  const long long g = *slot;
+  __syncthreads();  // every thread has read the slot before the next claim overwrites it
+  return g;
+}
+
 template <int TY, int NA, int NB, int NVS, int MODE, bool REFINE>
 __global__ __launch_bounds__(16 * TY) void fused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
-                                                                long long total) {
-  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+                                                                long long total, unsigned long long* queue) {
+  __shared__ long long slot;
+  for (long long g = next_system(queue, &slot); g < total; g = next_system(queue, &slot)) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -139,8 +151,9 @@ void bfused_kernel(const float2* __restrict__ snap,
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NW>())))
 void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
-                                                                 long long total) {
-  for (long long g = blockIdx.x; g < total; g += gridDim.x) {
+                                                                 long long total, unsigned long long* queue) {
+  __shared__ long long slot;
+  for (long long g = next_system(queue, &slot); g < total; g = next_system(queue, &slot)) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -155,14 +168,17 @@ void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
 }
 
 template <int TY, int NA, int NB, int NVS, int MODE>
-hipError_t go_fused_batched(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st) {
+hipError_t go_fused_batched(const ProbDesc* desc, int n, long long total, int refine, hipStream_t st,
+                            unsigned long long* queue) {
   // enough workgroups to fill every CU a few times over, never more than systems
   const long long want = 256LL * (TY == 16 ? 4 : 2);
   const dim3 grid((unsigned)(total < want ? total : want)), block(16 * TY);
   if (refine == 0)
-    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, false>), grid, block, 0, st, desc, n, total);
+    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, false>), grid, block, 0, st, desc, n, total,
+                       queue);
   else
-    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, true>), grid, block, 0, st, desc, n, total);
+    hipLaunchKernelGGL((fused_batched_kernel<TY, NA, NB, NVS, MODE, true>), grid, block, 0, st, desc, n, total,
+                       queue);
   return hipGetLastError();
 }
 

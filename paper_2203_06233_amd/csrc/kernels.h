@@ -33,9 +33,11 @@ int doppler_tiles(const Dims& d);
 hipError_t launch_doppler_batched(int P, const ProbDesc* desc, const BatchIndex& bi, int tiles, hipStream_t st);
 
 // Persistent fused covariance -> solve over every system of every cube of the
-// table (all fused_supported, one precision); `cls` is the largest D and S.
+// table (all fused_supported, one precision; max_dof / max_steer the largest
+// D and S): workgroups take systems from the work queue `queue`, a counter
+// that must be zero at launch.
 hipError_t launch_fused_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,
-                                int prec, int refine, int ty, hipStream_t st);
+                                int prec, int refine, int ty, hipStream_t st, unsigned long long* queue);
 
 // Inner products over every system of every cube of the table.
 hipError_t launch_inner_batched(const ProbDesc* desc, int n, long long total_sys, int max_dof, int max_steer,

@@ -109,7 +109,7 @@ def tune_workload(wl, precision, refine, reps=10, warmup=3):
     cube = torch.from_numpy(synth.make_cube(wl)).to(dev)
     V = torch.from_numpy(synth.steering(wl)).to(dev)
     prob = stap.problem(wl.n_chan, wl.n_pulse, wl.n_range, wl.tdof, wl.n_block, wl.n_steer,
-                        load_eps=wl.load_eps, precision=precision, refine_steps=refine)
+                        load_eps=wl.load_eps, precision=precision, refine_steps=refine, n_sub=wl.n_sub)
     runner = stap.Runner([prob], device=dev)
     power = torch.empty((wl.n_pulse, wl.n_steer, wl.n_range), dtype=torch.float32, device=dev)
     W = torch.empty((wl.n_pulse, wl.n_block, wl.n_steer, wl.dof), dtype=torch.complex64, device=dev)
@@ -155,7 +155,7 @@ def tune_kernel(wl, precision, refine, kind, reps=10, warmup=3):
     cube = torch.from_numpy(synth.make_cube(wl)).to(dev)
     V = torch.from_numpy(synth.steering(wl)).to(dev)
     prob = stap.problem(wl.n_chan, wl.n_pulse, wl.n_range, wl.tdof, wl.n_block, wl.n_steer,
-                        load_eps=wl.load_eps, precision=precision, refine_steps=refine)
+                        load_eps=wl.load_eps, precision=precision, refine_steps=refine, n_sub=wl.n_sub)
     snap = stap.doppler(prob, cube)
     if kind == KINDS["cov"]:
         cov, delta = stap.covariance(prob, snap)
@@ -193,7 +193,8 @@ def tune_kernel(wl, precision, refine, kind, reps=10, warmup=3):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="all", choices=["all", "small", "medium", "large", "xlarge", "uneven"])
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "small", "medium", "large", "xlarge", "uneven", "paper"])
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=CACHE)
     args = ap.parse_args()
@@ -201,8 +202,9 @@ def main():
     sys.path.insert(0, root)
     import synth
 
+    # the paper's cube shape class (D = 60, S = 32) on a 3000-cell slice of it
     sel = {"small": [synth.SMALL], "medium": [synth.MEDIUM], "large": [synth.LARGE], "xlarge": [synth.XLARGE],
-           "uneven": synth.uneven_batch(8)}
+           "uneven": synth.uneven_batch(8), "paper": [synth.with_(synth.PAPER, n_range=3000, n_block=25)]}
     wls = sum(sel.values(), []) if args.workload == "all" else sel[args.workload]
     a = arch()
     cache = load_cache(args.out)
