@@ -31,13 +31,14 @@ struct FftShape {
   static constexpr int LOG = ilog2(P);
   static constexpr int P1 = 1 << ((LOG + 1) / 2);
   static constexpr int P2 = P / P1;
-  static constexpr int RT = 256 / P2;  // range cells per workgroup
+  static constexpr int NT = 256;       // threads per workgroup
+  static constexpr int RT = NT / P2;   // range cells per workgroup
 };
-// The paper's 100 pulses: 10 x 10, 25 cells per workgroup (250 of the 256
-// threads take a column in the first pass).
+// The paper's 100 pulses: 10 x 10 on 320 threads, 32 cells per workgroup, so
+// that every wave reads whole 128-byte lines of two pulse rows.
 template <>
 struct FftShape<100> {
-  static constexpr int P1 = 10, P2 = 10, RT = 25;
+  static constexpr int P1 = 10, P2 = 10, NT = 320, RT = 32;
 };
 
 // One workgroup's tile: channel c, range cells r0 .. r0+RT-1 of one cube.
@@ -45,14 +46,14 @@ template <int P>
 __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, float2* __restrict__ snap,
                                              const Dims& d, int c, int r0) {
   using Sh = FftShape<P>;
-  constexpr int P1 = Sh::P1, P2 = Sh::P2, RT = Sh::RT;
+  constexpr int P1 = Sh::P1, P2 = Sh::P2, RT = Sh::RT, NT = Sh::NT;
   __shared__ float2 ybuf[P1 * P2 * RT];  // [k1][n2][cell]
   __shared__ float2 tw[P];
   __shared__ float hwin[P];
 
   const int tid = threadIdx.x;
 
-  for (int m = tid; m < P; m += 256) {
+  for (int m = tid; m < P; m += NT) {
     tw[m] = make_float2(kTwTab<P>.c[m], -kTwTab<P>.s[m]);
     hwin[m] = kWinTab<P>.h[d.T - 1][m];
   }
@@ -69,8 +70,28 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
     for (int n1 = 0; n1 < P1; ++n1) x[n1] = src[(long long)(P2 * n1 + n2) * d.sp];
   } else if (live) {
     // channel c is the sum of array elements c*sub .. c*sub + sub - 1,
-    // added in element order
-    for (int e = 0; e < d.sub; ++e) {
+    // added in element order; the loads of four elements are issued before
+    // their additions so that enough of them are in flight to stream the
+    // cube
+    constexpr int EU = 4;
+    int e = 0;
+    for (; e + EU <= d.sub; e += EU) {
+      float2 v[EU][P1];
+#pragma unroll
+      for (int u = 0; u < EU; ++u) {
+        const float2* src = cube + (long long)(c * d.sub + e + u) * d.sc + r;
+#pragma unroll
+        for (int n1 = 0; n1 < P1; ++n1) v[u][n1] = src[(long long)(P2 * n1 + n2) * d.sp];
+      }
+#pragma unroll
+      for (int u = 0; u < EU; ++u)
+#pragma unroll
+        for (int n1 = 0; n1 < P1; ++n1) {
+          x[n1].x += v[u][n1].x;
+          x[n1].y += v[u][n1].y;
+        }
+    }
+    for (; e < d.sub; ++e) {
       const float2* src = cube + (long long)(c * d.sub + e) * d.sc + r;
 #pragma unroll
       for (int n1 = 0; n1 < P1; ++n1) {
@@ -100,7 +121,7 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
     }
     __syncthreads();
     const int dof = t * d.C + c;
-    for (int task = tid; task < P1 * RT; task += 256) {
+    for (int task = tid; task < P1 * RT; task += NT) {
       const int c3 = task % RT, k1 = task / RT;
       float2 z[P2];
 #pragma unroll
@@ -123,14 +144,14 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void doppler_kernel(const float2* __restrict__ cube,
+__global__ __launch_bounds__(FftShape<P>::NT) void doppler_kernel(const float2* __restrict__ cube,
                                                       float2* __restrict__ snap, Dims d) {
   doppler_tile<P>(cube, snap, d, blockIdx.y, blockIdx.x * FftShape<P>::RT);
 }
 
 // Batched: the workgroups of several cubes with the same P in one grid.
 template <int P>
-__global__ __launch_bounds__(256) void doppler_batched_kernel(const ProbDesc* __restrict__ desc, BatchIndex bi) {
+__global__ __launch_bounds__(FftShape<P>::NT) void doppler_batched_kernel(const ProbDesc* __restrict__ desc, BatchIndex bi) {
   constexpr int RT = FftShape<P>::RT;
   const int g = blockIdx.x;
   int j = 0;
@@ -159,30 +180,30 @@ int doppler_tiles(const Dims& d) {
 hipError_t launch_doppler_batched(int P, const ProbDesc* desc, const BatchIndex& bi, int tiles, hipStream_t st) {
   if (tiles <= 0) return hipSuccess;
   switch (P) {
-    case 32: hipLaunchKernelGGL(doppler_batched_kernel<32>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
-    case 64: hipLaunchKernelGGL(doppler_batched_kernel<64>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
-    case 100: hipLaunchKernelGGL(doppler_batched_kernel<100>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
-    case 128: hipLaunchKernelGGL(doppler_batched_kernel<128>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
-    case 256: hipLaunchKernelGGL(doppler_batched_kernel<256>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
-    case 512: hipLaunchKernelGGL(doppler_batched_kernel<512>, dim3(tiles), dim3(256), 0, st, desc, bi); break;
+    case 32: hipLaunchKernelGGL(doppler_batched_kernel<32>, dim3(tiles), dim3(FftShape<32>::NT), 0, st, desc, bi); break;
+    case 64: hipLaunchKernelGGL(doppler_batched_kernel<64>, dim3(tiles), dim3(FftShape<64>::NT), 0, st, desc, bi); break;
+    case 100: hipLaunchKernelGGL(doppler_batched_kernel<100>, dim3(tiles), dim3(FftShape<100>::NT), 0, st, desc, bi); break;
+    case 128: hipLaunchKernelGGL(doppler_batched_kernel<128>, dim3(tiles), dim3(FftShape<128>::NT), 0, st, desc, bi); break;
+    case 256: hipLaunchKernelGGL(doppler_batched_kernel<256>, dim3(tiles), dim3(FftShape<256>::NT), 0, st, desc, bi); break;
+    case 512: hipLaunchKernelGGL(doppler_batched_kernel<512>, dim3(tiles), dim3(FftShape<512>::NT), 0, st, desc, bi); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_doppler(const Dims& d, const float2* cube, float2* snap, hipStream_t st) {
-  auto go = [&](auto kern, int rt) {
+  auto go = [&](auto kern, int rt, int nt) {
     dim3 grid((d.R + rt - 1) / rt, d.C);
-    hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, cube, snap, d);
+    hipLaunchKernelGGL(kern, grid, dim3(nt), 0, st, cube, snap, d);
     return hipGetLastError();
   };
   switch (d.P) {
-    case 32: return go(doppler_kernel<32>, FftShape<32>::RT);
-    case 64: return go(doppler_kernel<64>, FftShape<64>::RT);
-    case 100: return go(doppler_kernel<100>, FftShape<100>::RT);
-    case 128: return go(doppler_kernel<128>, FftShape<128>::RT);
-    case 256: return go(doppler_kernel<256>, FftShape<256>::RT);
-    case 512: return go(doppler_kernel<512>, FftShape<512>::RT);
+    case 32: return go(doppler_kernel<32>, FftShape<32>::RT, FftShape<32>::NT);
+    case 64: return go(doppler_kernel<64>, FftShape<64>::RT, FftShape<64>::NT);
+    case 100: return go(doppler_kernel<100>, FftShape<100>::RT, FftShape<100>::NT);
+    case 128: return go(doppler_kernel<128>, FftShape<128>::RT, FftShape<128>::NT);
+    case 256: return go(doppler_kernel<256>, FftShape<256>::RT, FftShape<256>::NT);
+    case 512: return go(doppler_kernel<512>, FftShape<512>::RT, FftShape<512>::NT);
   }
   return hipErrorInvalidValue;
 }
