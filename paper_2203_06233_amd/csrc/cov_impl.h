@@ -5,8 +5,9 @@
 //
 // 16x16 output tiles of the lower block triangle are spread over the NW waves
 // of the workgroup; range cells are staged through LDS in chunks of 32.
-//   MODE 0 (FP32)  v_mfma_f32_16x16x4_f32 on the complex64 snapshots; the four
-//                  real product terms accumulate separately within a chunk.
+//   MODE 0 (FP32)  v_mfma_f32_16x16x4_f32 on the complex64 snapshots, three
+//                  real products per complex product (Gauss) up to 128 DOF,
+//                  four beyond, accumulated separately within a chunk.
 //   MODE 1 (BF16)  every FP32 component is split exactly into three BF16
 //                  terms x = h + m + l; the six products hh, hm, mh, hl, lh, mm
 //                  run on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, hh
@@ -205,17 +206,34 @@ __device__ __forceinline__ void cov_accumulate(const float2* __restrict__ X, lon
         if (MODE == 0) {
           const float2* xs = reinterpret_cast<const float2*>(lds);
           const int kq = (nc + 3) & ~3;
-          floatx4 rr = floatx4{0.f, 0.f, 0.f, 0.f}, ii = rr, ir = rr, ri = rr;
-          for (int kk = 0; kk < kq; kk += 4) {
-            const float2 a = xs[ra * F32_PITCH + kk + (lane >> 4)];
-            const float2 bb = xs[rb * F32_PITCH + kk + (lane >> 4)];
-            rr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, rr, 0, 0, 0);
-            ii = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ii, 0, 0, 0);
-            ir = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, ir, 0, 0, 0);
-            ri = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.y, ri, 0, 0, 0);
+          floatx4 rr = floatx4{0.f, 0.f, 0.f, 0.f}, ii = rr, tt = rr, ri = rr;
+          if constexpr (DP <= 128) {
+            // Gauss's three-product form: with A = Xr, B = Xi of the row
+            // blocks, T1 = A A^T, T2 = B B^T, T3 = (A + B)(A - B)^T give
+            // Re = T1 + T2 and Im = B A^T - A B^T = T3 - T1 + T2
+            for (int kk = 0; kk < kq; kk += 4) {
+              const float2 a = xs[ra * F32_PITCH + kk + (lane >> 4)];
+              const float2 bb = xs[rb * F32_PITCH + kk + (lane >> 4)];
+              rr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, rr, 0, 0, 0);
+              ii = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ii, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, bb.x - bb.y, tt, 0, 0, 0);
+            }
+            accR[i] += rr + ii;
+            accI[i] += (tt - rr) + ii;
+          } else {
+            // four products (T3 would push the 192-DOF tiles over the
+            // register budget): tt = B A^T, ri = A B^T
+            for (int kk = 0; kk < kq; kk += 4) {
+              const float2 a = xs[ra * F32_PITCH + kk + (lane >> 4)];
+              const float2 bb = xs[rb * F32_PITCH + kk + (lane >> 4)];
+              rr = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.x, rr, 0, 0, 0);
+              ii = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.y, ii, 0, 0, 0);
+              tt = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bb.x, tt, 0, 0, 0);
+              ri = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bb.y, ri, 0, 0, 0);
+            }
+            accR[i] += rr + ii;
+            accI[i] += tt - ri;
           }
-          accR[i] += rr + ii;
-          accI[i] += ir - ri;
         } else if (MODE == 1) {
           const uint4* pl = reinterpret_cast<const uint4*>(lds);
           constexpr int PS4 = DP * BF_PITCH / 8;

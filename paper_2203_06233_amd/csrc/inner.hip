@@ -245,8 +245,12 @@ __global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ w
   inner_system<ST, DP, RTW>(wts, snap, power, yout, d, blockIdx.x);
 }
 
+// With two steering tiles and one range tile per wave step the register
+// allocation fits three workgroups per compute unit (164 VGPRs at D = 96,
+// no spills): more snapshot loads in flight for this bandwidth-bound pass.
 template <int ST, int DP, int RTW>
-__global__ __launch_bounds__(256) void inner_bf16_kernel(const float2* __restrict__ wts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == 2 && RTW == 1 && DP >= 64 ? 3 : 1)))
+void inner_bf16_kernel(const float2* __restrict__ wts,
                                                          const float2* __restrict__ snap,
                                                          float* __restrict__ power, float2* __restrict__ yout,
                                                          Dims d) {
