@@ -70,10 +70,11 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
     for (int n1 = 0; n1 < P1; ++n1) x[n1] = src[(long long)(P2 * n1 + n2) * d.sp];
   } else if (live) {
     // channel c is the sum of array elements c*sub .. c*sub + sub - 1,
-    // added in element order; the loads of four elements are issued before
-    // their additions so that enough of them are in flight to stream the
-    // cube
-    constexpr int EU = 4;
+    // added in element order; with few samples per thread the loads of four
+    // elements are issued before their additions so that enough of them are
+    // in flight to stream the cube (more would cost the registers that set
+    // the occupancy of the whole kernel)
+    constexpr int EU = P1 <= 10 ? 4 : 1;
     int e = 0;
     for (; e + EU <= d.sub; e += EU) {
       float2 v[EU][P1];
@@ -143,15 +144,20 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
   }
 }
 
+// More workgroups per compute unit for more loads in flight, where the
+// registers allow it without spills: three at 256 pulses (168 VGPRs), three
+// 320-thread groups at 100 pulses (128 VGPRs).
 template <int P>
-__global__ __launch_bounds__(FftShape<P>::NT) void doppler_kernel(const float2* __restrict__ cube,
+__global__ __launch_bounds__(FftShape<P>::NT) __attribute__((amdgpu_waves_per_eu(P == 256 ? 3 : P == 100 ? 4 : 1)))
+void doppler_kernel(const float2* __restrict__ cube,
                                                       float2* __restrict__ snap, Dims d) {
   doppler_tile<P>(cube, snap, d, blockIdx.y, blockIdx.x * FftShape<P>::RT);
 }
 
 // Batched: the workgroups of several cubes with the same P in one grid.
 template <int P>
-__global__ __launch_bounds__(FftShape<P>::NT) void doppler_batched_kernel(const ProbDesc* __restrict__ desc, BatchIndex bi) {
+__global__ __launch_bounds__(FftShape<P>::NT) __attribute__((amdgpu_waves_per_eu(P == 256 ? 3 : P == 100 ? 4 : 1)))
+void doppler_batched_kernel(const ProbDesc* __restrict__ desc, BatchIndex bi) {
   constexpr int RT = FftShape<P>::RT;
   const int g = blockIdx.x;
   int j = 0;

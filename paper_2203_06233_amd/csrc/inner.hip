@@ -239,8 +239,11 @@ __device__ __forceinline__ void inner_bf16_system(const float2* __restrict__ wts
   }
 }
 
+// Two steering tiles and two range tiles per step fit 128 VGPRs at 32..128
+// DOF without spills: four workgroups per compute unit instead of three.
 template <int ST, int DP, int RTW>
-__global__ __launch_bounds__(256) void inner_kernel(const float2* __restrict__ wts, const float2* __restrict__ snap,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == 2 && RTW == 2 && DP >= 32 && DP <= 128 ? 4 : 1)))
+void inner_kernel(const float2* __restrict__ wts, const float2* __restrict__ snap,
                                                     float* __restrict__ power, float2* __restrict__ yout, Dims d) {
   inner_system<ST, DP, RTW>(wts, snap, power, yout, d, blockIdx.x);
 }
@@ -258,8 +261,11 @@ void inner_bf16_kernel(const float2* __restrict__ wts,
 }
 
 // Batched: one workgroup per system of every cube of the table.
+// The same register budgets as the single-cube kernels for two steering
+// tiles.
 template <int ST, int DP, bool BF>
-__global__ __launch_bounds__(256) void inner_batched_kernel(const ProbDesc* __restrict__ desc, int n) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST != 2 ? 1 : BF ? (DP >= 64 ? 3 : 1) : (DP >= 32 ? 4 : 1))))
+void inner_batched_kernel(const ProbDesc* __restrict__ desc, int n) {
   const long long g = blockIdx.x;
   int lo = 0, hi = n - 1;
   while (lo < hi) {
