@@ -1,11 +1,18 @@
-// Fused covariance -> blocked matrix-core solve, FP32 covariance products.
+// Fused covariance -> blocked matrix-core solve, FP32 covariance products:
+// the one-cube launches, 8-wave shapes here (lane offsets kept live), 4-wave
+// shapes in bfused_f32_w4.hip.
+#define STAP_TID_DIRECT
 #include "bfused_launch.h"
 
 namespace stap {
 
+hipError_t launch_bfused_f32_w4(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
+                                 hipStream_t st, int waves);
+
 hipError_t launch_bfused_f32(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info,
-                            hipStream_t st, int waves) {
-  return bfused::single<0>(d, snap, steer, w, info, st, waves);
+                              hipStream_t st, int waves) {
+  if (bfused::pick_waves(d.D, waves) == 4) return launch_bfused_f32_w4(d, snap, steer, w, info, st, waves);
+  return bfused::single<0, 8>(d, snap, steer, w, info, st, waves);
 }
 
 }  // namespace stap

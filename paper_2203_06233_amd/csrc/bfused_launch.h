@@ -69,11 +69,23 @@ hipError_t pick(int D, int S, int waves, F&& f) {
   return hipErrorInvalidValue;
 }
 
-template <int MODE>
+// The wave count pick() takes for D and the requested waves.
+inline int pick_waves(int D, int waves) {
+  const int nb = (D + 15) / 16;
+  return nb <= 4 ? 4 : nb <= 6 ? (waves == 8 ? 8 : 4) : 8;
+}
+
+// One-cube launches of the shapes that run on NWSEL waves (the 4- and 8-wave
+// kernels live in separate translation units, built with different
+// lane_tid() forms).
+template <int MODE, int NWSEL>
 hipError_t single(const Dims& d, const float2* snap, const float2* steer, float2* w, int* info, hipStream_t st,
                   int waves) {
-  return pick<MODE>(d.D, d.S, waves, [&](auto nb, auto ns, auto nw) {
-    return go1<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(d, snap, steer, w, info, st);
+  return pick<MODE>(d.D, d.S, waves, [&](auto nb, auto ns, auto nw) -> hipError_t {
+    if constexpr (decltype(nw)::value == NWSEL)
+      return go1<decltype(nb)::value, decltype(ns)::value, decltype(nw)::value, MODE>(d, snap, steer, w, info, st);
+    else
+      return hipErrorInvalidValue;
   });
 }
 

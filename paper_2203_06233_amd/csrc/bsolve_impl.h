@@ -51,7 +51,7 @@ __device__ __forceinline__ int bofs(int r, int c) {
 }
 
 __device__ __forceinline__ Frag frag_load(const float2* blk) {
-  const int l = threadIdx.x & 63;
+  const int l = lane_tid() & 63;
   const float4 a = *reinterpret_cast<const float4*>(blk + 2 * l);
   const float4 b = *reinterpret_cast<const float4*>(blk + 128 + 2 * l);
   Frag f;
@@ -62,13 +62,13 @@ __device__ __forceinline__ Frag frag_load(const float2* blk) {
   return f;
 }
 __device__ __forceinline__ void frag_store(float2* blk, const Frag& f) {
-  const int l = threadIdx.x & 63;
+  const int l = lane_tid() & 63;
   *reinterpret_cast<float4*>(blk + 2 * l) = make_float4(f.v[0].x, f.v[0].y, f.v[1].x, f.v[1].y);
   *reinterpret_cast<float4*>(blk + 128 + 2 * l) = make_float4(f.v[2].x, f.v[2].y, f.v[3].x, f.v[3].y);
 }
 // Store X^T: the lane's X[m][4q + i] goes to element (4q + i, m).
 __device__ __forceinline__ void frag_store_t(float2* blk, const Frag& f) {
-  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+  const int l = lane_tid() & 63, m = l & 15, q = l >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) blk[bofs(4 * q + i, m)] = f.v[i];
 }
@@ -211,7 +211,7 @@ __device__ __forceinline__ void diag_cols(Frag& A, Frag& X, int m, float& rsm, i
 // broadcast); only l_mj crosses rows.  Returns 0 or the 1-based index of the
 // first non-positive pivot.
 __device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X, double p64) {
-  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+  const int l = lane_tid() & 63, m = l & 15, q = l >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
   int fail = 0;
@@ -226,7 +226,7 @@ __device__ __forceinline__ int diag_factor_inv(Frag& A, Frag& X, double p64) {
 // holds X[m][4q + i]; the element (m, m) sits in lane q = m / 4, register
 // m % 4), or 0 on the other lanes.
 __device__ __forceinline__ float frag_diag(const Frag& A) {
-  const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+  const int l = lane_tid() & 63, m = l & 15, q = l >> 4;
   float v = 0.f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) v = (m == 4 * q + i) ? A.v[i].x : v;
@@ -299,14 +299,14 @@ __device__ __forceinline__ void bs_factor_diag(Acc (&acc)[NSL], const float (&rd
     mma_pqh<true>(a, P, P);
     A = to_frag(a);
   }
-  const int m = threadIdx.x & 15;
+  const int m = lane_tid() & 15;
   const double p64 = (double)rd - (Jd > 0 ? d64[16 * Jd + m] : 0.0);
   const int f = diag_factor_inv(A, X, p64);
   frag_store(dinv, X);
 #pragma unroll
   for (int t = 0; t < NSL; ++t)
     if (td == t) acc[t] = to_acc(X);
-  if ((threadIdx.x & 63) == 0) *sflag = f ? 16 * Jd + f : 0;
+  if ((lane_tid() & 63) == 0) *sflag = f ? 16 * Jd + f : 0;
 }
 
 __device__ __forceinline__ doublex4 mfma64(double a, double b, doublex4 c) {
@@ -342,7 +342,7 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
   double* gpart = reinterpret_cast<double*>(xlds + C::xblocks(NB, NS) * 256 * 8);
   int* sflag = reinterpret_cast<int*>(gpart + NB * 16 * NS);
   double* d64 = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(sflag) + 16);
-  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, q = lane >> 4;
+  const int tid = lane_tid(), lane = tid & 63, m = lane & 15, q = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   float2* dinv = xb + (size_t)(NB + NS) * 256;
 

@@ -9,6 +9,25 @@
 
 namespace stap {
 
+// The thread index as the solve code reads it.  By default threadIdx.x is
+// passed through an empty volatile asm statement: the dozens of per-lane
+// offsets derived from it are then recomputed where they are used instead
+// of being computed once and kept live in registers across the whole kernel
+// (or, in a persistent kernel, across every system it takes), which the
+// register allocator otherwise pays for with spills.  Where keeping them
+// live measures faster (the 8-wave one-cube fused kernels, the one-wave
+// solve), the translation unit defines STAP_TID_DIRECT before any include.
+__device__ __forceinline__ int lane_tid() {
+#ifdef STAP_TID_DIRECT
+  return (int)threadIdx.x;
+#else
+  int t;
+  asm volatile("" : "=v"(t) : "0"((int)threadIdx.x));
+  return t;
+#endif
+}
+
+
 constexpr int kMaxDof = 192;
 constexpr int kMaxSteer = 64;
 constexpr int kMaxTdof = 4;

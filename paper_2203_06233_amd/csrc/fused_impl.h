@@ -70,7 +70,7 @@ __global__ __launch_bounds__(16 * TY) void fused_kernel(const float2* __restrict
 // out first and the cheap ones fill in behind them.  Every workgroup leaves
 // when the counter has passed the last system.
 __device__ __forceinline__ long long next_system(unsigned long long* queue, long long* slot) {
-  if (threadIdx.x == 0) *slot = (long long)atomicAdd(queue, 1ULL);
+  if (lane_tid() == 0) *slot = (long long)atomicAdd(queue, 1ULL);
   __syncthreads();
   const long long g = *slot;
   __syncthreads();  // every thread has read the slot before the next claim overwrites it
@@ -135,12 +135,16 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
 
 // With 8 waves and up to 6 block columns the register allocation is capped
 // at 128 so that two systems share a compute unit (with refinement a few
-// registers spill).
-template <int NB, int NW>
-constexpr int bfused_min_waves() { return NW == 8 && NB <= 6 ? 4 : 1; }
+// registers spill).  In the one-cube kernel with 4 waves, up to 4 block
+// columns and up to 2 block rows of steering vectors it is capped at 168
+// (no spills): three systems per compute unit instead of two.
+template <int NB, int NS, int NW, bool BATCHED>
+constexpr int bfused_min_waves() {
+  return NW == 8 && NB <= 6 ? 4 : !BATCHED && NW == 4 && NB <= 4 && NS <= 2 ? 3 : 1;
+}
 
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NS, NW, false>())))
 void bfused_kernel(const float2* __restrict__ snap,
                                                          const float2* __restrict__ steer,
                                                          float2* __restrict__ wout, int* __restrict__ info_out,
@@ -149,7 +153,7 @@ void bfused_kernel(const float2* __restrict__ snap,
 }
 
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NW>())))
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(bfused_min_waves<NB, NS, NW, true>())))
 void bfused_batched_kernel(const ProbDesc* __restrict__ desc, int n,
                                                                  long long total, unsigned long long* queue) {
   __shared__ long long slot;

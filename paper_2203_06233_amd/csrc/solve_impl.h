@@ -74,7 +74,7 @@ template <class K>
 __device__ __forceinline__ void sweep_back(float2 (&x)[K::NVS][K::NB], const float2 (&lm)[K::NA][K::NB],
                                            int D, SolveShared<K>& sh) {
   constexpr int TY = K::TY, NB = K::NB, NVS = K::NVS;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tx = lane_tid() & 15, ty = lane_tid() >> 4;
   __syncthreads();
 #pragma unroll
   for (int jb = NB - 1; jb >= 0; --jb) {
@@ -117,7 +117,7 @@ template <class K>
 __device__ __forceinline__ void sweep_fwd(float2 (&x)[K::NVS][K::NB], const float2 (&lm)[K::NA][K::NB],
                                           int D, SolveShared<K>& sh) {
   constexpr int TY = K::TY, NA = K::NA, NB = K::NB, NVS = K::NVS;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tx = lane_tid() & 15, ty = lane_tid() >> 4;
   __syncthreads();
 #pragma unroll
   for (int jb = 0; jb < NB; ++jb) {
@@ -169,7 +169,7 @@ __device__ __forceinline__ void residual_mfma(const RSrc& src, const float2* Rp,
                                               const float2* __restrict__ steer, int D, int S) {
   constexpr int TY = K::TY, NB = K::NB, NVS = K::NVS, NW = K::NT / 64;
   constexpr int NI = (NB + NW - 1) / NW;  // output row blocks per wave
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = lane_tid(), tx = tid & 15, ty = tid >> 4;
   const int lane = tid & 63, wave = tid >> 6, m16 = lane & 15, q = lane >> 4;
   const int nslab = (S + 15) >> 4;
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ __forceinline__ void solve_system(const RSrc& src, const float2* Rp, 
                                              const float2* __restrict__ steer, float2* __restrict__ W,
                                              int* __restrict__ info, const Dims& d, SolveShared<K>& sh) {
   constexpr int TY = K::TY, NA = K::NA, NB = K::NB, NVS = K::NVS, NT = K::NT, DPC = K::DPC;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = lane_tid(), tx = tid & 15, ty = tid >> 4;
   const int D = d.D, S = d.S;
 
   float2 lm[NA][NB];

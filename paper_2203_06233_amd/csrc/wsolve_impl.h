@@ -164,7 +164,7 @@ __device__ __forceinline__ void diag_cols_work(Frag& A, Frag& X, int m, float& r
 template <int NB, int NS, int J>
 __device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[NS * NB], int& fail, double* d64,
                                           const float* rdiag) {
-  const int lane = threadIdx.x & 63;
+  const int lane = lane_tid() & 63;
 #pragma unroll
   for (int I = J + 1; I < NB; ++I) {
     Acc x = acc_zero();
@@ -181,7 +181,7 @@ __device__ __forceinline__ void fact_step(Acc (&L)[NB * (NB + 1) / 2], Acc (&M)[
   }
   if constexpr (J + 1 < NB) {
     pqh<true>(L[tri(J + 1, J + 1)], L[tri(J + 1, J)], L[tri(J + 1, J)]);
-    const int l = threadIdx.x & 63, m = l & 15, q = l >> 4;
+    const int l = lane_tid() & 63, m = l & 15, q = l >> 4;
     Frag A = to_frag(L[tri(J + 1, J + 1)]), X;
 #pragma unroll
     for (int i = 0; i < 4; ++i) X.v[i] = make_float2(m == 4 * q + i ? 1.f : 0.f, 0.f);
@@ -223,7 +223,7 @@ __device__ __forceinline__ void wsolve_system(const float2* __restrict__ R, cons
   using LY = WsLds<NB, REFINE>;
   constexpr int NL = NB * (NB + 1) / 2;
   const int D = d.D, S = d.S;
-  const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
+  const int lane = lane_tid() & 63, m = lane & 15, q = lane >> 4;
   float2* tb = lds;
   float2* Rp = lds + LY::SLOTS * 256;
   double* d64 = reinterpret_cast<double*>(Rp + LY::PACK);

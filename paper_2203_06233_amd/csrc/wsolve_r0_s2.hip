@@ -1,4 +1,5 @@
 // One-wave stage solve, steering class 2 (S <= 32), refinement off.
+#define STAP_TID_DIRECT
 #include "wsolve_launch.h"
 
 namespace stap {
