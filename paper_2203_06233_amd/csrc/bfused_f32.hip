@@ -1,7 +1,8 @@
 // Fused covariance -> blocked matrix-core solve, FP32 covariance products:
-// the one-cube launches, 8-wave shapes here (lane offsets kept live), 4-wave
-// shapes in bfused_f32_w4.hip.
+// the one-cube launches, 8-wave shapes here (lane offsets kept live, the
+// residual's operands loaded ahead), 4-wave shapes in bfused_f32_w4.hip.
 #define STAP_TID_DIRECT
+#define STAP_RESIDUAL_LOADS_AHEAD
 #include "bfused_launch.h"
 
 namespace stap {

@@ -33,6 +33,20 @@
 
 namespace stap {
 
+// The FP64 refinement residual either loads the operands of a block column's
+// four k-steps before their products (more registers, less exposed LDS
+// latency) or interleaves loads and products step by step.  Measured: the
+// first is faster in the 8-wave one-cube fused kernel (7.16 -> 7.03 ms on
+// the 32 x 256 x 16384 cube), the second in the persistent batched one
+// (48.0 against 50.0 ms on the uneven batch); translation units choose with
+// STAP_RESIDUAL_LOADS_AHEAD.
+#ifdef STAP_RESIDUAL_LOADS_AHEAD
+constexpr bool kResidualLoadsAhead = true;
+#else
+constexpr bool kResidualLoadsAhead = false;
+#endif
+
+
 struct Frag {
   float2 v[4];
 };
@@ -559,22 +573,38 @@ __device__ __forceinline__ void bsolve_system(const RSrc& src, const float2* __r
           doublex4 a1 = {0.0, 0.0, 0.0, 0.0}, a2 = a1, a3 = a1;
           const float2* zrow = xb + (size_t)mr[t] * NB * 256 + 2 * lane;
           const int c = 16 * mc[t] + m;
+          // R_L[r][c] for r = 16 J + 4 q + s4, c = 16 I + m (identity beyond D)
+          auto r_elem = [&](int J, int s4) {
+            const int r = 16 * J + 4 * q + s4;
+            float2 rv;
+            if (r < D && c < D) {
+              rv = c <= r ? src.lower(r, c) : src.lower(c, r);
+              rv.y = c <= r ? rv.y : -rv.y;
+            } else {
+              rv = make_float2(r == c ? 1.f : 0.f, 0.f);
+            }
+            return rv;
+          };
+          auto acc3 = [&](float2 rv, float2 z) {
+            const double qr = rv.x, qi = rv.y, pr = z.x, pi = z.y;
+            a1 = mfma64(qr, pr, a1);
+            a2 = mfma64(qi, pi, a2);
+            a3 = mfma64(qr + qi, pr + pi, a3);
+          };
           for (int J = 0; J < NB; ++J) {
-#pragma unroll 1
-            for (int s4 = 0; s4 < 4; ++s4) {
-              const float2 z = zrow[J * 256 + (s4 & 2) * 64 + (s4 & 1)];  // Z_{N,J}[m][4q + s4]
-              const int r = 16 * J + 4 * q + s4;                         // R[r][c], c = 16 I + m
-              float2 rv;
-              if (r < D && c < D) {
-                rv = c <= r ? src.lower(r, c) : src.lower(c, r);
-                rv.y = c <= r ? rv.y : -rv.y;
-              } else {
-                rv = make_float2(r == c ? 1.f : 0.f, 0.f);
+            if constexpr (kResidualLoadsAhead) {
+              // the four k-steps' operands loaded before their products
+              float2 zz[4], rr[4];
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) {
+                zz[s4] = zrow[J * 256 + (s4 & 2) * 64 + (s4 & 1)];  // Z_{N,J}[m][4q + s4]
+                rr[s4] = r_elem(J, s4);
               }
-              const double qr = rv.x, qi = rv.y, pr = z.x, pi = z.y;
-              a1 = mfma64(qr, pr, a1);
-              a2 = mfma64(qi, pi, a2);
-              a3 = mfma64(qr + qi, pr + pi, a3);
+#pragma unroll
+              for (int s4 = 0; s4 < 4; ++s4) acc3(rr[s4], zz[s4]);
+            } else {
+#pragma unroll 1
+              for (int s4 = 0; s4 < 4; ++s4) acc3(r_elem(J, s4), zrow[J * 256 + (s4 & 2) * 64 + (s4 & 1)]);
             }
           }
           const doublex4 cr = a1 - a2, ci = a3 - a1 - a2;
