@@ -208,10 +208,12 @@ stap_status stap_inner_products(const stap_problem* prob, const stap_cf32* w,
  *              256-byte aligned; its contents on entry are ignored.
  * All problems must share precision and refine_steps.  With n_probs > 1 and
  * every cube fused-eligible (D <= 128, FP32 or BF16) the batch runs as one
- * Doppler launch per pulse count, one persistent covariance->solve launch
- * whose workgroups take the (cube, bin, block) systems, most expensive
- * first, from a device work queue, and one inner-product launch; the problem
- * table (136 bytes per cube, plus the queue counter) is written into the
+ * Doppler launch per pulse count, then per shape class (DOF class x
+ * steering class, largest first) one persistent covariance->solve launch
+ * sized for the class, whose workgroups take the class's (cube, bin, block)
+ * systems, most expensive first, from a device work queue, and one
+ * inner-product launch per class; the problem table (136 bytes per cube,
+ * then 24 queue counters of 8 bytes) is written into the
  * workspace by a kernel that carries it in its arguments, and the launch
  * chain is replayed from a cached hipGraph (a stream that is being captured
  * gets the launches directly, table kernel included).  Batches with a cube

@@ -174,9 +174,15 @@ Parts parts_of(const stap_problem* q) {
   p.info = up(P * B * 4);
   return p;
 }
-// The problem table of a batch, then the 8-byte work-queue counter of the
-// persistent covariance -> solve kernel.
-size_t table_bytes(int n) { return up((size_t)n * sizeof(stap::ProbDesc) + sizeof(unsigned long long)); }
+// A batch is split into shape classes (DOF class x steering class), each
+// with its own persistent covariance -> solve launch and inner-product
+// launch sized for it.  The workspace starts with the problem table, then
+// one 8-byte work-queue counter per class.
+constexpr int kMaxClasses = 8 * 3;
+int shape_class(const Dims& d) { return dof_class(d.D) * 3 + steer_class(d.S); }
+size_t table_bytes(int n) {
+  return up((size_t)n * sizeof(stap::ProbDesc) + kMaxClasses * sizeof(unsigned long long));
+}
 
 // Per-system cost used to order a batch (largest first).
 double system_cost(const Dims& d) {
@@ -228,14 +234,14 @@ struct TableChunk {
 };
 static_assert(sizeof(stap::ProbDesc) % 8 == 0, "table entries are copied as 8-byte words");
 
-// The first chunk's launch also resets the work-queue counter (a kernel
-// store, so a captured graph resets it on every replay).
+// The first chunk's launch also resets the work-queue counters (kernel
+// stores, so a captured graph resets them on every replay).
 __global__ void table_kernel(stap::ProbDesc* __restrict__ table, TableChunk c, unsigned long long* queue) {
   const int words = c.n * (int)(sizeof(stap::ProbDesc) / 8);
   const unsigned long long* src = reinterpret_cast<const unsigned long long*>(c.d);
   unsigned long long* dst = reinterpret_cast<unsigned long long*>(table + c.first);
   for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
-  if (c.first == 0 && threadIdx.x == 0) *queue = 0ULL;
+  if (c.first == 0 && threadIdx.x < kMaxClasses) queue[threadIdx.x] = 0ULL;
 }
 
 hipError_t upload_table(stap::ProbDesc* table, const std::vector<stap::ProbDesc>& desc, unsigned long long* queue,
@@ -333,22 +339,36 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
     return STAP_OK;
   }
 
-  // Batched: order by per-system cost, number the systems, upload the table.
+  // Batched: group the cubes by shape class (largest class first), order
+  // each class by per-system cost, number its systems, upload the table.
   std::stable_sort(desc.begin(), desc.end(), [](const stap::ProbDesc& a, const stap::ProbDesc& b) {
+    const int ka = shape_class(a.d), kb = shape_class(b.d);
+    if (ka != kb) return ka > kb;
     return system_cost(a.d) > system_cost(b.d);
   });
-  long long total = 0;
-  int max_dof = 0, max_steer = 0;
-  for (auto& pd : desc) {
-    pd.sys_begin = total;
-    total += (long long)pd.d.P * pd.d.B;
-    max_dof = std::max(max_dof, pd.d.D);
-    max_steer = std::max(max_steer, pd.d.S);
+  struct Group {
+    int lo, n, key;
+    long long total;
+    int max_dof, max_steer, ty;
+  };
+  std::vector<Group> groups;
+  for (int i = 0; i < n_probs; ++i) {
+    stap::ProbDesc& pd = desc[i];
+    const int key = shape_class(pd.d);
+    if (groups.empty() || groups.back().key != key) groups.push_back(Group{i, 0, key, 0, 0, 0, 0});
+    Group& g = groups.back();
+    pd.sys_begin = g.total;
+    g.total += (long long)pd.d.P * pd.d.B;
+    g.max_dof = std::max(g.max_dof, pd.d.D);
+    g.max_steer = std::max(g.max_steer, pd.d.S);
+    ++g.n;
   }
-  Dims cls = desc[0].d;
-  cls.D = max_dof;
-  cls.S = max_steer;
-  const int ty = fused_variant(cls);
+  for (Group& g : groups) {
+    Dims cls = desc[g.lo].d;
+    cls.D = g.max_dof;
+    cls.S = g.max_steer;
+    g.ty = fused_variant(cls);
+  }
   const int prec = probs[0].precision, refine = probs[0].refine_steps;
 
   // Doppler launches, one per pulse count (at most kMaxBatchArg cubes each).
@@ -380,9 +400,17 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
       hipError_t e = stap::launch_doppler_batched(x.second, table, x.first, x.first.tile_begin[x.first.n], s);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = stap::launch_fused_batched(table, n_probs, total, max_dof, max_steer, prec, refine, ty, s, queue);
-    if (e != hipSuccess) return e;
-    return stap::launch_inner_batched(table, n_probs, total, max_dof, max_steer, prec, s);
+    for (size_t i = 0; i < groups.size(); ++i) {
+      const Group& g = groups[i];
+      const hipError_t e = stap::launch_fused_batched(table + g.lo, g.n, g.total, g.max_dof, g.max_steer, prec, refine,
+                                                      g.ty, s, queue + i);
+      if (e != hipSuccess) return e;
+    }
+    for (const Group& g : groups) {
+      const hipError_t e = stap::launch_inner_batched(table + g.lo, g.n, g.total, g.max_dof, g.max_steer, prec, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
 
   if (upload_table(table, desc, queue, st) != hipSuccess) return STAP_ERR_HIP;
@@ -393,7 +421,8 @@ stap_status run_impl(const stap_problem* probs, int32_t n_probs, const stap_cf32
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return STAP_ERR_HIP;
   std::string key = std::to_string(dev) + "|" + std::to_string((uintptr_t)ws0) + "|" +
-                    std::to_string(prec) + "|" + std::to_string(refine) + "|" + std::to_string(ty);
+                    std::to_string(prec) + "|" + std::to_string(refine);
+  for (const Group& g : groups) key += "|v" + std::to_string(g.ty);
   for (auto& pd : desc) {
     key += "|" + std::to_string(pd.d.C) + "," + std::to_string(pd.d.P) + "," + std::to_string(pd.d.R) + "," +
            std::to_string(pd.d.T) + "," + std::to_string(pd.d.B) + "," + std::to_string(pd.d.S);

@@ -16,7 +16,7 @@ struct ProbDesc {
   float2* w;
   int* info;
   float2* snap;
-  long long sys_begin;  // first global system index (problems ordered by cost)
+  long long sys_begin;  // first system index within the cube's shape class of the batch
 };
 
 // Kernel argument of a batched Doppler launch: up to kMaxBatchArg cubes with

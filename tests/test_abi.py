@@ -262,23 +262,24 @@ def test_workspace_size_formula(binding):
     def up(x):
         return (x + 255) // 256 * 256
     table = 136  # one problem descriptor (the kernels' copy of the shapes and pointers)
+    queues = 24 * 8  # a work-queue counter per shape class (8 DOF classes x 3 steering classes)
     per = up(P * D * R * 8) + up(P * B * S * D * 8) + up(P * B * 4)
     cov = up(P * B * D * D * 8) + up(P * B * 4)
     # D <= 96 and S <= 32: the one-wave stage route may run, covariance and delta included
-    assert binding.workspace_size([p]) == up(table) + per + cov
-    assert binding.workspace_size([p, p]) == up(2 * table) + 2 * (per + cov)
+    assert binding.workspace_size([p]) == up(table + queues) + per + cov
+    assert binding.workspace_size([p, p]) == up(2 * table + queues) + 2 * (per + cov)
     # D in (96, 128] takes the fused kernel: no covariance
     f = binding.problem(n_chan=40, n_pulse=32, n_range=256, tdof=3, n_block=2, n_steer=20)
     P, D, R, B, S = 32, 120, 256, 2, 20
     per_f = up(P * D * R * 8) + up(P * B * S * D * 8) + up(P * B * 4)
-    assert binding.workspace_size([f]) == up(table) + per_f
+    assert binding.workspace_size([f]) == up(table + queues) + per_f
     # D > 128 keeps the covariance and delta in the workspace
     q = binding.problem(n_chan=48, n_pulse=32, n_range=256, tdof=3, n_block=2, n_steer=20)
     P, D, R, B, S = 32, 144, 256, 2, 20
     per_q = (up(P * D * R * 8) + up(P * B * D * D * 8) + up(P * B * 4) + up(P * B * S * D * 8)
              + up(P * B * 4))
-    assert binding.workspace_size([q]) == up(table) + per_q
+    assert binding.workspace_size([q]) == up(table + queues) + per_q
     # FP8 does not use the fused kernel either
     p8 = binding.problem(**dict(GOOD, precision="fp8"))
     P, D, R, B, S = 64, 12, 512, 32, 8
-    assert binding.workspace_size([p8]) == up(table) + per + cov
+    assert binding.workspace_size([p8]) == up(table + queues) + per + cov
