@@ -101,6 +101,12 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
   __builtin_nontemporal_store(x, reinterpret_cast<f2v*>(p));
 }
 __device__ __forceinline__ void store_stream(float* p, float v) { __builtin_nontemporal_store(v, p); }
+// A read of data that is used once (streamed past the caches' retention).
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(x.x, x.y);
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -67,7 +67,7 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
   if (live && d.sub == 1) {
     const float2* src = cube + (long long)c * d.sc + r;
 #pragma unroll
-    for (int n1 = 0; n1 < P1; ++n1) x[n1] = src[(long long)(P2 * n1 + n2) * d.sp];
+    for (int n1 = 0; n1 < P1; ++n1) x[n1] = load_stream(src + (long long)(P2 * n1 + n2) * d.sp);
   } else if (live) {
     // channel c is the sum of array elements c*sub .. c*sub + sub - 1,
     // added in element order; with few samples per thread the loads of four
@@ -82,7 +82,7 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
       for (int u = 0; u < EU; ++u) {
         const float2* src = cube + (long long)(c * d.sub + e + u) * d.sc + r;
 #pragma unroll
-        for (int n1 = 0; n1 < P1; ++n1) v[u][n1] = src[(long long)(P2 * n1 + n2) * d.sp];
+        for (int n1 = 0; n1 < P1; ++n1) v[u][n1] = load_stream(src + (long long)(P2 * n1 + n2) * d.sp);
       }
 #pragma unroll
       for (int u = 0; u < EU; ++u)
@@ -96,7 +96,7 @@ __device__ __forceinline__ void doppler_tile(const float2* __restrict__ cube, fl
       const float2* src = cube + (long long)(c * d.sub + e) * d.sc + r;
 #pragma unroll
       for (int n1 = 0; n1 < P1; ++n1) {
-        const float2 v = src[(long long)(P2 * n1 + n2) * d.sp];
+        const float2 v = load_stream(src + (long long)(P2 * n1 + n2) * d.sp);
         x[n1].x += v.x;
         x[n1].y += v.y;
       }
