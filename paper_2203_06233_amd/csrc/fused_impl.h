@@ -135,12 +135,17 @@ __device__ __forceinline__ void bfused_system(const float2* __restrict__ snap, c
 
 // With 8 waves and up to 6 block columns the register allocation is capped
 // at 128 so that two systems share a compute unit (with refinement a few
-// registers spill).  In the one-cube kernel with 4 waves, up to 4 block
-// columns and up to 2 block rows of steering vectors it is capped at 168
-// (no spills): three systems per compute unit instead of two.
+// registers spill).  With 4 waves and up to 2 block rows of steering
+// vectors: the one-cube kernel is capped at 168 up to 4 block columns (three
+// systems per compute unit instead of two); the persistent batched kernel,
+// which left to itself holds more registers across its loop (up to 196),
+// at 128 up to 2 block columns and 168 at 3 (four and three systems per
+// compute unit) -- all without spills.
 template <int NB, int NS, int NW, bool BATCHED>
 constexpr int bfused_min_waves() {
-  return NW == 8 && NB <= 6 ? 4 : !BATCHED && NW == 4 && NB <= 4 && NS <= 2 ? 3 : 1;
+  if (NW == 8 && NB <= 6) return 4;
+  if (NW == 4 && NS <= 2) return BATCHED ? (NB <= 2 ? 4 : NB == 3 ? 3 : 1) : (NB <= 4 ? 3 : 1);
+  return 1;
 }
 
 template <int NB, int NS, int NSL, int NSM, int NW, int MODE, bool REFINE>
