@@ -261,10 +261,11 @@ void inner_bf16_kernel(const float2* __restrict__ wts,
 }
 
 // Batched: one workgroup per system of every cube of the table.
-// The same register budgets as the single-cube kernels for two steering
-// tiles.
+// Register budgets that fit without spills: 128 (four workgroups per CU)
+// for one steering tile and for FP32 with two, 168 (three) for split BF16
+// with two.
 template <int ST, int DP, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST != 2 ? 1 : BF ? (DP >= 64 ? 3 : 1) : (DP >= 32 ? 4 : 1))))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ST == 1 ? 4 : ST != 2 ? 1 : BF ? 3 : (DP >= 32 ? 4 : 1))))
 void inner_batched_kernel(const ProbDesc* __restrict__ desc, int n) {
   const long long g = blockIdx.x;
   int lo = 0, hi = n - 1;
